@@ -1,0 +1,236 @@
+"""Algorithm 1 (2-block standard ADMM) with the merged x-step -- oracle, test infrastructure.
+
+Sec. 3.1.  With the constraints scaled as in Sec. 5/6.1 (B = psi D, the control
+coupling k_u = psi * s with s = +-1, and the copy constraints on u scaled by
+e_u = psi; e_y = 1), one iteration j is:
+
+  1. R_y = rho (J1 yhat - e_y w_y + e_y^2 z_y / delta) + (1 - rho) B^T p
+     R_u = rho (-e_u w_u + e_u^2 z_u / delta) + (1 - rho) k_u p
+     M_y = rho (J1 + e_y^2/delta), M_u = rho (J2 + e_u^2/delta),
+     M_p = k_u^2 M_u^{-1} + (delta/rho) I                (all diagonal)
+     r   = k_u M_u^{-1} R_u - h + (delta/rho) p,   h = psi g
+  2. S y = R_y - B^T M_p^{-1} r,  S = M_y + B^T M_p^{-1} B   (eq. (3.9))
+  3. p = M_p^{-1}(B y + r),  u = M_u^{-1}(R_u - k_u p)
+  4. z_y = Proj_[ya,yb](y + delta w_y / e_y), z_u = Proj_[ua,ub](u + delta w_u / e_u)
+  5. w_y += (rho/delta) e_y (y - z_y),  w_u += (rho/delta) e_u (u - z_u)
+  6. stop when max(|B y + k_u u - h|_inf, |y - z_y|_inf, |u - z_u|_inf) <= tol
+
+Steps 1-3 are the elimination of u and p from the merged system (3.8); the
+sign of the M_u^{-1} term in r is "+" (eliminating u from the third block row
+gives + k_u M_u^{-1} R_u; the printed "-" does not reproduce the block solve,
+which tests/test_oracle_admm.py checks).  Step 4 is the closed form of the
+z-subproblem (3.6b); step 5 is (3.6d); p is updated inside step 3, which is
+(3.6c) merged into the x-step.  The normal equations are solved by textbook
+PCG (Sec. 6.1 uses MATLAB pcg) with the preconditioner S~ of eq. (3.10).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import operator as op
+from .precond import apply_precond, precond_tables
+
+
+@dataclasses.dataclass
+class Scalars:
+    psi: float
+    e_y: float
+    e_u: float
+    k_u: float
+    wts: np.ndarray  # (nt,) diagonal of J1 per time slice
+    My: np.ndarray  # (nt,)
+    Mu: np.ndarray  # (nt,)
+    Mp: np.ndarray  # (nt,)
+
+
+def objective_weights(w) -> np.ndarray:
+    """J1 = diag(wts) (x) I: all ones, or trapezoidal with 1/2 on the last
+    time block (eq. (4.10))."""
+    wts = np.ones(w.nt)
+    if w.obj_weights == 1:
+        wts[-1] = 0.5
+    return wts
+
+
+def scalars(w, d: op.Disc) -> Scalars:
+    psi = op.psi_scale(d) if w.psi_scaling else 1.0
+    e_y = 1.0
+    e_u = psi if w.psi_scaling else 1.0
+    k_u = psi * w.ctrl_sign
+    wts = objective_weights(w)
+    My = w.rho * (wts + e_y ** 2 / w.delta)
+    Mu = w.rho * (w.gamma * wts + e_u ** 2 / w.delta)
+    Mp = k_u ** 2 / Mu + w.delta / w.rho
+    return Scalars(psi, e_y, e_u, k_u, wts, My, Mu, Mp)
+
+
+def tcol(a):
+    """Broadcast a per-time-slice vector over (nt, ny, nx)."""
+    return np.asarray(a)[:, None, None]
+
+
+def apply_B(d, sc, v):
+    return sc.psi * op.apply_D(d, v)
+
+
+def apply_BT(d, sc, v):
+    return sc.psi * op.apply_DT(d, v)
+
+
+def apply_S(d, sc, v):
+    """S v = M_y v + B^T M_p^{-1} B v (eq. (3.9), scaled form)."""
+    return tcol(sc.My) * v + apply_BT(d, sc, apply_B(d, sc, v) / tcol(sc.Mp))
+
+
+def pcg(A, M, b, x0, tol, maxit):
+    """Textbook preconditioned CG (Fletcher-Reeves beta), stopping on the
+    recursively updated residual: ||r||_2 <= tol ||b||_2.  Returns
+    (x, iterations, relative residual, converged)."""
+    normb = math.sqrt(float(np.vdot(b, b)))
+    if normb == 0.0:
+        return np.zeros_like(b), 0, 0.0, True
+    x = x0.copy()
+    r = b - A(x)
+    normr = math.sqrt(float(np.vdot(r, r)))
+    if normr <= tol * normb:
+        return x, 0, normr / normb, True
+    z = M(r)
+    p = z.copy()
+    rz = float(np.vdot(r, z))
+    for k in range(1, maxit + 1):
+        q = A(p)
+        alpha = rz / float(np.vdot(p, q))
+        x = x + alpha * p
+        r = r - alpha * q
+        normr = math.sqrt(float(np.vdot(r, r)))
+        if normr <= tol * normb:
+            return x, k, normr / normb, True
+        z = M(r)
+        rz_new = float(np.vdot(r, z))
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    return x, maxit, normr / normb, False
+
+
+@dataclasses.dataclass
+class AdmmResult:
+    y: np.ndarray
+    u: np.ndarray
+    zy: np.ndarray
+    zu: np.ndarray
+    p: np.ndarray
+    wy: np.ndarray
+    wu: np.ndarray
+    iters: int
+    pcg_iters: list
+    r_p: float
+    r_y: float
+    r_u: float
+    converged: bool
+    psi: float
+
+
+def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
+               krylov_tol: Optional[float] = None, state=None) -> AdmmResult:
+    """Run Algorithm 1 on workload `w` from all-zero iterates (or `state`).
+
+    iters   -- if given, run exactly this many iterations (no stopping test)
+    solver  -- "pcg" (PCG with S~, warm-started from the previous y) or
+               "direct" (dense Cholesky of S; tiny grids only)
+    """
+    d = op.disc_from(w)
+    sc = scalars(w, d)
+    tab = precond_tables(w, d)
+    shape = w.shape
+    yhat = np.asarray(w.yhat, dtype=np.float64)
+    g = np.zeros(shape) if w.g is None else np.asarray(w.g, dtype=np.float64)
+    h = sc.psi * g
+    if state is None:
+        y, u, zy, zu, p, wy, wu = (np.zeros(shape) for _ in range(7))
+    else:
+        y, u, zy, zu, p, wy, wu = (np.array(a, dtype=np.float64) for a in state)
+    ktol = w.krylov_tol if krylov_tol is None else krylov_tol
+    J1 = tcol(sc.wts)
+    My, Mu, Mp = tcol(sc.My), tcol(sc.Mu), tcol(sc.Mp)
+    rho, delta = w.rho, w.delta
+
+    Schol = None
+    if solver == "direct":
+        D = op.assemble_D(d)
+        Bm = sc.psi * D
+        S = np.diag(np.repeat(sc.My, w.nx * w.ny)) + Bm.T @ np.diag(1.0 / np.repeat(sc.Mp, w.nx * w.ny)) @ Bm
+        Schol = np.linalg.cholesky(S)
+
+    A = lambda v: apply_S(d, sc, v)
+    M = lambda v: apply_precond(tab, v)
+    pcg_counts = []
+    maxit = w.admm_maxit if iters is None else iters
+    r_p = r_y = r_u = math.inf
+    converged = False
+    j = 0
+    for j in range(1, maxit + 1):
+        # 1. right-hand sides of the merged system (3.8)
+        Ry = rho * (J1 * yhat - sc.e_y * wy + sc.e_y ** 2 * zy / delta) + (1 - rho) * apply_BT(d, sc, p)
+        Ru = rho * (-sc.e_u * wu + sc.e_u ** 2 * zu / delta) + (1 - rho) * sc.k_u * p
+        r = sc.k_u * Ru / Mu - h + (delta / rho) * p
+        b = Ry - apply_BT(d, sc, r / Mp)
+        # 2. normal equations (3.9)
+        if solver == "pcg":
+            y, it, _, _ = pcg(A, M, b, y, ktol, w.krylov_maxit)
+            pcg_counts.append(it)
+        else:
+            Lc = Schol
+            y = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b.ravel())).reshape(shape)
+            pcg_counts.append(0)
+        # 3. recover p (dual update merged into the x-step) and u
+        By = apply_B(d, sc, y)
+        p = (By + r) / Mp
+        u = (Ru - sc.k_u * p) / Mu
+        # 4. z-step: projection onto the box
+        zy = np.clip(y + delta * wy / sc.e_y, w.ya, w.yb)
+        zu = np.clip(u + delta * wu / sc.e_u, w.ua, w.ub)
+        # 5. dual updates
+        wy = wy + (rho / delta) * sc.e_y * (y - zy)
+        wu = wu + (rho / delta) * sc.e_u * (u - zu)
+        # 6. termination test (Sec. 6.1)
+        r_p = float(np.max(np.abs(By + sc.k_u * u - h)))
+        r_y = float(np.max(np.abs(y - zy)))
+        r_u = float(np.max(np.abs(u - zu)))
+        if iters is None and max(r_p, r_y, r_u) <= w.admm_tol:
+            converged = True
+            break
+    return AdmmResult(y=y, u=u, zy=zy, zu=zu, p=p, wy=wy, wu=wu, iters=j, pcg_iters=pcg_counts,
+                      r_p=r_p, r_y=r_y, r_u=r_u, converged=converged, psi=sc.psi)
+
+
+def xstep_block_solve(w, yhat, zy, zu, p, wy, wu, g=None):
+    """Reference for steps 1-3: solve the merged 3x3 block system (3.8) densely
+    for (y, u, p+) in the scaled variables (tiny grids only)."""
+    d = op.disc_from(w)
+    sc = scalars(w, d)
+    N = w.N
+    Bm = sc.psi * op.assemble_D(d)
+    J1 = np.repeat(sc.wts, w.nx * w.ny)
+    J2 = w.gamma * J1
+    rho, delta = w.rho, w.delta
+    I = np.eye(N)
+    g = np.zeros(N) if g is None else g.ravel()
+    K = np.block([
+        [np.diag(rho * (J1 + sc.e_y ** 2 / delta)), np.zeros((N, N)), Bm.T],
+        [np.zeros((N, N)), np.diag(rho * (J2 + sc.e_u ** 2 / delta)), sc.k_u * I],
+        [Bm, sc.k_u * I, -(delta / rho) * I],
+    ])
+    rhs = np.concatenate([
+        rho * (J1 * yhat.ravel() - sc.e_y * wy.ravel() + sc.e_y ** 2 * zy.ravel() / delta)
+        + (1 - rho) * Bm.T @ p.ravel(),
+        rho * (-sc.e_u * wu.ravel() + sc.e_u ** 2 * zu.ravel() / delta) + (1 - rho) * sc.k_u * p.ravel(),
+        sc.psi * g - (delta / rho) * p.ravel(),
+    ])
+    sol = np.linalg.solve(K, rhs)
+    shp = w.shape
+    return sol[:N].reshape(shp), sol[N:2 * N].reshape(shp), sol[2 * N:].reshape(shp)

@@ -1,0 +1,177 @@
+"""The discretised fractional-diffusion constraint matrix D -- oracle, test infrastructure.
+
+Sec. 4: D = C_t (x) I - I (x) (L_x (+) L_y), eq. (4.9), with
+  * time: implicit Euler, i.e. the Grünwald matrix of eq. (4.5) at order 1:
+    C_t = (I - Z) / h_t with Z the sub-diagonal shift and y(t=0) = 0;
+  * space: the shifted (p = 1) Grünwald matrix of eq. (4.6),
+    G[i, j] = g_{i-j+1} for i-j+1 >= 0, and the two-sided operator
+    L_a = (c_a / h^a) (diag(d+) G + diag(d-) G^T), c_a the Riesz factor of
+    eq. (4.7).  With d+ = d- = 1 this is exactly the paper's Riesz matrix;
+    the row scaling by a coefficient field is the variable-coefficient
+    reading (coefficient outside the derivative).
+Fields are arrays of shape (nt, ny, nx) (x fastest).  Products along x use
+G on the last axis, products along y on the middle axis: dense matrix
+products, no FFT.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+from .grunwald import riesz_factor, weights
+
+
+@dataclasses.dataclass
+class Disc:
+    nx: int
+    ny: int
+    nt: int
+    hx: float
+    hy: float
+    ht: float
+    alpha: float
+    beta: float
+    dplus: np.ndarray  # (ny, nx)
+    dminus: np.ndarray  # (ny, nx)
+
+
+def disc_from(w) -> Disc:
+    """Mesh sizes h_x = 1/(nx+1), h_y = 1/(ny+1), h_t = T/nt (Sec. 6.1 grid)."""
+    ones = np.ones((w.ny, w.nx))
+    dp = ones if w.dplus is None else np.asarray(w.dplus, dtype=np.float64)
+    dm = ones if w.dminus is None else np.asarray(w.dminus, dtype=np.float64)
+    return Disc(nx=w.nx, ny=w.ny, nt=w.nt, hx=1.0 / (w.nx + 1), hy=1.0 / (w.ny + 1),
+                ht=w.T / w.nt, alpha=w.alpha, beta=w.beta, dplus=dp, dminus=dm)
+
+
+def shifted_grunwald(a: float, n: int, g: np.ndarray | None = None) -> np.ndarray:
+    """n x n left shifted Grünwald matrix of eq. (4.6) without the 1/h^a factor:
+    entry (i, j) is g_{i-j+1} when i-j+1 >= 0, else 0.  `g` overrides the
+    weights (used with derivative weights)."""
+    if g is None:
+        g = weights(a, n)
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    k = i - j + 1
+    return np.where(k >= 0, g[np.clip(k, 0, n)], 0.0)
+
+
+def time_matrix(nt: int, ht: float) -> np.ndarray:
+    """Implicit Euler: (I - Z) / h_t (eq. (4.5) at order 1: g = (1, -1, 0, ...))."""
+    return (np.eye(nt) - np.eye(nt, k=-1)) / ht
+
+
+# --- line-wise applies -------------------------------------------------------
+def apply_E(d: Disc, v):
+    out = v.copy()
+    out[1:] -= v[:-1]
+    return out / d.ht
+
+
+def apply_ET(d: Disc, v):
+    out = v.copy()
+    out[:-1] -= v[1:]
+    return out / d.ht
+
+
+def apply_Lx(d: Disc, v, transpose=False):
+    """L_x along every x-line (t, j): row scaling by d+/d- of that line."""
+    G = shifted_grunwald(d.alpha, d.nx)
+    s = riesz_factor(d.alpha) / d.hx ** d.alpha
+    if not transpose:
+        # (G v)_i = sum_k G[i,k] v_k ; (G^T v)_i = sum_k G[k,i] v_k
+        return s * (d.dplus * (v @ G.T) + d.dminus * (v @ G))
+    return s * ((d.dplus * v) @ G + (d.dminus * v) @ G.T)
+
+
+def apply_Ly(d: Disc, v, transpose=False):
+    """L_y along every y-line (t, i)."""
+    G = shifted_grunwald(d.beta, d.ny)
+    s = riesz_factor(d.beta) / d.hy ** d.beta
+    if not transpose:
+        return s * (d.dplus * np.matmul(G, v) + d.dminus * np.matmul(G.T, v))
+    return s * (np.matmul(G.T, d.dplus * v) + np.matmul(G, d.dminus * v))
+
+
+def apply_D(d: Disc, v):
+    """D v = C_t v - L_x v - L_y v (eq. (4.9))."""
+    return apply_E(d, v) - apply_Lx(d, v) - apply_Ly(d, v)
+
+
+def apply_DT(d: Disc, v):
+    """D^T v."""
+    return apply_ET(d, v) - apply_Lx(d, v, True) - apply_Ly(d, v, True)
+
+
+# --- dense assembly (small grids) -------------------------------------------
+def line_matrix(a, h, n, dp_line, dm_line, g=None):
+    G = shifted_grunwald(a, n, g)
+    return riesz_factor(a) / h ** a * (np.diag(dp_line) @ G + np.diag(dm_line) @ G.T)
+
+
+def assemble_D(d: Disc) -> np.ndarray:
+    """Dense D by Kronecker assembly of eq. (4.9); index (t*ny + j)*nx + i."""
+    nx, ny, nt = d.nx, d.ny, d.nt
+    M = nx * ny
+    Lx = np.zeros((M, M))
+    Ly = np.zeros((M, M))
+    for j in range(ny):
+        Lj = line_matrix(d.alpha, d.hx, nx, d.dplus[j, :], d.dminus[j, :])
+        Lx[j * nx:(j + 1) * nx, j * nx:(j + 1) * nx] = Lj
+    for i in range(nx):
+        Li = line_matrix(d.beta, d.hy, ny, d.dplus[:, i], d.dminus[:, i])
+        idx = np.arange(ny) * nx + i
+        Ly[np.ix_(idx, idx)] = Li
+    return np.kron(time_matrix(nt, d.ht), np.eye(M)) - np.kron(np.eye(nt), Lx + Ly)
+
+
+def assemble_D_sparse(d: Disc):
+    """The same matrix as scipy.sparse CSR (used for the active-set polish)."""
+    import scipy.sparse as sp
+
+    nx, ny, nt = d.nx, d.ny, d.nt
+    M = nx * ny
+    blocks_x = [sp.csr_matrix(line_matrix(d.alpha, d.hx, nx, d.dplus[j, :], d.dminus[j, :]))
+                for j in range(ny)]
+    Lx = sp.block_diag(blocks_x, format="csr")
+    rows, cols, vals = [], [], []
+    for i in range(nx):
+        Li = line_matrix(d.beta, d.hy, ny, d.dplus[:, i], d.dminus[:, i])
+        jj, kk = np.nonzero(Li)
+        rows.append(jj * nx + i)
+        cols.append(kk * nx + i)
+        vals.append(Li[jj, kk])
+    Ly = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(M, M))
+    Ct = sp.csr_matrix(time_matrix(nt, d.ht))
+    return (sp.kron(Ct, sp.identity(M)) - sp.kron(sp.identity(nt), Lx + Ly)).tocsr()
+
+
+def psi_scale(d: Disc) -> float:
+    """psi = min{h_t, h_x^alpha, h_y^beta} (Sec. 5, time order 1)."""
+    return min(d.ht, d.hx ** d.alpha, d.hy ** d.beta)
+
+
+def sampled_D(d: Disc, v, points):
+    """(D v) at the listed (t, j, i) points only, from the point's own row of D:
+    its x-line, its y-line and its time neighbour.  Cost O(nx + ny) per point."""
+    ga = weights(d.alpha, d.nx)
+    gb = weights(d.beta, d.ny)
+    sx = riesz_factor(d.alpha) / d.hx ** d.alpha
+    sy = riesz_factor(d.beta) / d.hy ** d.beta
+    out = np.empty(len(points))
+    for n, (t, j, i) in enumerate(points):
+        # row i of G: entries g_{i-k+1} for k <= i+1 ; row i of G^T: g_{k-i+1} for k >= i-1
+        k = np.arange(d.nx)
+        rowG = np.where(i - k + 1 >= 0, ga[np.clip(i - k + 1, 0, d.nx)], 0.0)
+        rowGT = np.where(k - i + 1 >= 0, ga[np.clip(k - i + 1, 0, d.nx)], 0.0)
+        lx = sx * (d.dplus[j, i] * rowG @ v[t, j, :] + d.dminus[j, i] * rowGT @ v[t, j, :])
+        k = np.arange(d.ny)
+        rowG = np.where(j - k + 1 >= 0, gb[np.clip(j - k + 1, 0, d.ny)], 0.0)
+        rowGT = np.where(k - j + 1 >= 0, gb[np.clip(k - j + 1, 0, d.ny)], 0.0)
+        ly = sy * (d.dplus[j, i] * rowG @ v[t, :, i] + d.dminus[j, i] * rowGT @ v[t, :, i])
+        prev = v[t - 1, j, i] if t > 0 else 0.0
+        out[n] = (v[t, j, i] - prev) / d.ht - lx - ly
+    return out

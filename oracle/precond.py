@@ -1,0 +1,105 @@
+"""T. Chan circulants and the Schur-complement preconditioner -- oracle, test infrastructure.
+
+Sec. 5: the T. Chan (Frobenius-optimal) circulant of a Toeplitz matrix T_n has
+first column c_i = ((n-i) t_i + i t_{i-n}) / n (closed form under eq. (5.1)),
+and its eigenvalues are the DFT of c (Thm 2.2).  The 3-level circulant
+C_3(B) of eq. (5.2) has the separable eigenvalues
+    Lambda = psi (lambda_t[k] - lambda_y[j] - lambda_x[i]).
+Sec. 3.2, eq. (3.10): with circulant blocks and J_1 approximated by the
+scalar jbar = 1 (the paper notes J is nearly a scaled identity, Sec. 4),
+    S~ = rho (jbar + e_y^2/delta) I + C_3(B)^* C_3(B) / mbar_p,
+    mbar_p = k_u^2 / (rho (gamma jbar + e_u^2/delta)) + delta/rho,
+so S~ has eigenvalues s = a + |Lambda|^2 / mbar_p in the DFT basis.
+
+DFT convention: lambda_k = sum_m c_m exp(-2 pi i k m / n), computed here by the
+explicit O(n^2) sum; the circulant acts as C x = F^{-1} diag(lambda) F x with
+F[k, m] = exp(-2 pi i k m / n) and F^{-1} = conj(F) / n.  Variable
+coefficients enter the preconditioner through their arithmetic means over
+the interior nodes.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .grunwald import riesz_factor
+from .operator import Disc, psi_scale, shifted_grunwald, time_matrix
+
+
+def tchan_column(T: np.ndarray) -> np.ndarray:
+    """First column of the T. Chan circulant of the Toeplitz matrix T
+    (t_k = T[k, 0] for k >= 0, t_{-k} = T[0, k])."""
+    n = T.shape[0]
+    c = np.empty(n, dtype=T.dtype)
+    for i in range(n):
+        t_i = T[i, 0]
+        t_i_minus_n = T[0, n - i] if i > 0 else 0.0
+        c[i] = ((n - i) * t_i + i * t_i_minus_n) / n
+    return c
+
+
+def dft_matrix(n: int) -> np.ndarray:
+    """F[k, m] = exp(-2 pi i k m / n), with k*m reduced mod n first (exact)."""
+    k = np.arange(n)
+    return np.exp(-2j * np.pi * (np.outer(k, k) % n) / n)
+
+
+def dft_eigenvalues(c: np.ndarray) -> np.ndarray:
+    """lambda_k = sum_m c_m exp(-2 pi i k m / n), explicit sum."""
+    return dft_matrix(len(c)) @ c
+
+
+def circulant(c: np.ndarray) -> np.ndarray:
+    """Dense circulant with first column c: C[i, j] = c[(i - j) mod n]."""
+    n = len(c)
+    i = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return c[(i - j) % n]
+
+
+def mean_line_operator(a, h, n, dbar_plus, dbar_minus):
+    """Constant-coefficient (mean-coefficient) spatial Toeplitz matrix."""
+    G = shifted_grunwald(a, n)
+    return riesz_factor(a) / h ** a * (dbar_plus * G + dbar_minus * G.T)
+
+
+def precond_tables(w, d: Disc):
+    """Eigenvalue tables and scalars of S~ (Sec. 5, eq. (5.2); eq. (3.10))."""
+    dbp = float(np.mean(d.dplus))
+    dbm = float(np.mean(d.dminus))
+    Lx = mean_line_operator(d.alpha, d.hx, d.nx, dbp, dbm)
+    Ly = mean_line_operator(d.beta, d.hy, d.ny, dbp, dbm)
+    Ct = time_matrix(d.nt, d.ht)
+    col_x, col_y, col_t = tchan_column(Lx), tchan_column(Ly), tchan_column(Ct)
+    lam_x = dft_eigenvalues(col_x)
+    lam_y = dft_eigenvalues(col_y)
+    lam_t = dft_eigenvalues(col_t)
+    psi = psi_scale(d) if w.psi_scaling else 1.0
+    e_y = 1.0
+    e_u = psi if w.psi_scaling else 1.0
+    k_u = psi * w.ctrl_sign
+    jbar = 1.0
+    a = w.rho * (jbar + e_y ** 2 / w.delta)
+    mbar_p = k_u ** 2 / (w.rho * (w.gamma * jbar + e_u ** 2 / w.delta)) + w.delta / w.rho
+    return dict(lam_x=lam_x, lam_y=lam_y, lam_t=lam_t, col_x=col_x, col_y=col_y, col_t=col_t,
+                psi=psi, a=a, mbar_p=mbar_p)
+
+
+def precond_symbol(tab) -> np.ndarray:
+    """s[k, j, i] = a + |psi (lam_t[k] - lam_y[j] - lam_x[i])|^2 / mbar_p."""
+    lam = tab["psi"] * (tab["lam_t"][:, None, None] - tab["lam_y"][None, :, None]
+                        - tab["lam_x"][None, None, :])
+    return tab["a"] + np.abs(lam) ** 2 / tab["mbar_p"]
+
+
+def apply_precond(tab, r: np.ndarray) -> np.ndarray:
+    """z = S~^{-1} r with dense DFT matrices along each axis (no FFT)."""
+    nt, ny, nx = r.shape
+    Fx, Fy, Ft = dft_matrix(nx), dft_matrix(ny), dft_matrix(nt)
+    R = r.astype(np.complex128) @ Fx.T  # along x
+    R = np.matmul(Fy, R)  # along y
+    R = np.tensordot(Ft, R, axes=([1], [0]))  # along t
+    R = R / precond_symbol(tab)
+    Z = np.tensordot(np.conj(Ft), R, axes=([1], [0])) / nt
+    Z = np.matmul(np.conj(Fy), Z) / ny
+    Z = Z @ np.conj(Fx).T / nx
+    return Z.real.copy()
