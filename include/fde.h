@@ -1,0 +1,190 @@
+/*
+ * fde.h -- C ABI of the MI355X (gfx950) hot path of ADMM for box-constrained
+ * optimal control under a time-dependent 2-D fractional-diffusion constraint.
+ *
+ * Method: Pougkakiotis, Pearson, Leveque, Gondzio, "Fast Solution Methods for
+ * Convex Fractional Differential Equation Optimization".  The discretised
+ * problem is the QP of Sec. 3 (eq. (3.3)) with the constraint of Sec. 4:
+ *
+ *     min  1/2 (y - yhat)^T J1 (y - yhat) + 1/2 u^T J2 u,     J2 = gamma J1
+ *     s.t. D y + s u = g,   ya <= y <= yb,   ua <= u <= ub,
+ *
+ *     D = C_t (x) I - I (x) (L_x (+) L_y)                        (eq. (4.9))
+ *
+ * with implicit Euler in time (the Grünwald matrix of eq. (4.5) at order 1),
+ * shifted Grünwald two-sided operators L_a = (c_a/h^a)(diag(d+) G_a +
+ * diag(d-) G_a^T) in space (eqs. (4.6)-(4.7)), c_a = -1/(2 cos(a pi/2)).
+ *
+ * Conventions for every entry point:
+ *   - Fields are contiguous float64 arrays of nx*ny*nt values, layout
+ *     [nt][ny][nx] (x fastest); index (k*ny + j)*nx + i is the node
+ *     (x_i, y_j, t_k) = ((i+1) hx, (j+1) hy, (k+1) ht), hx = 1/(nx+1),
+ *     hy = 1/(ny+1), ht = T/nt.
+ *   - Field pointers are DEVICE pointers owned by the caller (e.g. a torch
+ *     tensor's data_ptr()); pointers marked (host) are host memory.  The
+ *     library never frees caller memory.  A context owns only its O(n)
+ *     tables and its workspace (about 12 fields plus a half spectrum).
+ *   - Work is enqueued on the context's stream.  Calls returning host
+ *     results (iteration counts, stats) synchronise that stream; the others
+ *     are asynchronous.  A context must be used by one host thread and one
+ *     stream at a time.
+ *   - Return value: FDE_OK, a positive warning (FDE_ENOTCONV: the iteration
+ *     limit was reached, outputs hold the last iterate) or a negative error.
+ *     After an error the outputs are unspecified and fde_last_error() gives
+ *     a message (thread-local).  Parameter errors are detected before any
+ *     device work is enqueued.
+ */
+#ifndef FDE_H
+#define FDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fde_ctx fde_ctx;
+
+typedef enum {
+  FDE_OK = 0,
+  FDE_ENOTCONV = 1,      /* warning: iteration limit reached                  */
+  FDE_EINVAL = -1,       /* invalid parameter or unsupported size             */
+  FDE_ENOMEM = -2,       /* device allocation failed                           */
+  FDE_EHIP = -3,         /* HIP runtime error (no device, launch failure ...)  */
+  FDE_ENONFINITE = -4    /* NaN/Inf met in a residual                          */
+} fde_status;
+
+/* Problem description (Sec. 4, eqs. (4.2)-(4.10)). */
+typedef struct {
+  int32_t nx, ny, nt;     /* interior nodes per axis; each 2^a 3^b with b <= 1,
+                             4 <= n <= 1024                                     */
+  double T;               /* final time (> 0); ht = T / nt                      */
+  double alpha, beta;     /* fractional orders along x and y, each in (1, 2]    */
+  const double* dplus;    /* (host) ny*nx coefficient field d+, row j = y_j;
+                             NULL means d+ = 1.  Copied at create time.        */
+  const double* dminus;   /* (host) same for d-                                 */
+  double ctrl_sign;       /* s = +1: D y + u = g (eq. (4.8)); -1: D y - u = g    */
+  int32_t psi_scaling;    /* 1: scale the constraints by psi = min{ht, hx^alpha,
+                             hy^beta} and the copies of u by psi (Sec. 5, 6.1);
+                             0: unscaled                                        */
+  int32_t obj_weights;    /* 0: J1 = I; 1: trapezoidal, 1/2 on the last time
+                             block (eq. (4.10))                                 */
+  int32_t precond_fp32;   /* 1: run the circulant preconditioner in float32
+                             (operator, residuals, dots, ADMM stay float64)     */
+} fde_problem;
+
+/* ADMM and Krylov settings (Algorithm 1; Sec. 6.1). */
+typedef struct {
+  double gamma;           /* > 0, J2 = gamma J1                                 */
+  double delta;           /* > 0, the augmented term is 1/(2 delta)||.||^2      */
+  double rho;             /* dual step, in (0, (1 + sqrt 5)/2)                   */
+  double ya, yb, ua, ub;  /* bounds, +-INFINITY allowed, ya <= yb, ua <= ub     */
+  double krylov_tol;      /* PCG stops when ||r||_2 <= tol ||b||_2              */
+  int32_t krylov_maxit;   /* > 0                                                */
+  int32_t tol_mode;       /* 0: fixed krylov_tol; 1: the paper's dynamic rule
+                             0.05 max{min{three residuals}, 1e-4}              */
+  double admm_tol;        /* stop when max of the three inf-norm residuals
+                             <= admm_tol (0: run exactly admm_maxit iterations) */
+  int32_t admm_maxit;     /* > 0                                                */
+} fde_admm_params;
+
+typedef struct {
+  int32_t admm_iters;     /* iterations performed                                */
+  int32_t pcg_total;      /* PCG iterations summed over all x-steps              */
+  int32_t pcg_last;       /* PCG iterations of the last x-step                   */
+  int32_t pcg_max;        /* largest PCG count of one x-step                     */
+  double r_p;             /* ||B y + k_u u - psi g||_inf  (scaled constraint)     */
+  double r_y;             /* ||y - z_y||_inf                                      */
+  double r_u;             /* ||u - z_u||_inf                                      */
+  double t_total;         /* seconds, wall clock of the solve                    */
+  double t_pcg;           /* seconds spent in the Krylov solves (host clock)     */
+} fde_admm_stats;
+
+/* Check a problem/parameter pair without touching the GPU.  FDE_OK or
+ * FDE_EINVAL (message in fde_last_error()). */
+fde_status fde_validate(const fde_problem* prob, const fde_admm_params* prm);
+
+/* Host-only setup tables, for inspection and CPU tests (no GPU use).
+ * Writes (host, caller-allocated):
+ *   scal[8]         = {psi, hx, hy, ht, a, 1/mbar_p, e_u, k_u}
+ *   lam_x[2*nx], lam_y[2*ny], lam_t[2*nt]  interleaved (re, im) T. Chan
+ *                     eigenvalues, lambda_k = sum_m c_m exp(-2 pi i k m / n)
+ *                     (Sec. 5, closed form under eq. (5.1) and Thm 2.2);
+ *   gx[nx+1], gy[ny+1] Grünwald weights of orders alpha, beta (Sec. 4).
+ * Any output pointer may be NULL. */
+fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, double* scal,
+                           double* lam_x, double* lam_y, double* lam_t, double* gx, double* gy);
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t
+ * (NULL = default stream).  Validates, builds the weights, embedding and
+ * T. Chan eigen tables and twiddles on the host (FP64), copies them to the
+ * device and allocates the workspace.  *out receives the context. */
+fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream,
+                      fde_ctx** out);
+fde_status fde_destroy(fde_ctx* ctx);
+
+/* Replace the ADMM/Krylov settings of a context (same validation as create;
+ * gamma, delta, rho enter the preconditioner tables, which are rebuilt). */
+fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm);
+
+/* y = D x (transpose = 0) or y = D^T x (transpose = 1), the unscaled
+ * constraint matrix of eq. (4.9), by circulant embedding and FFT (Table 1).
+ * x and y are device fields and must not alias. */
+fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose);
+
+/* y = S x with S = M_y + B^T M_p^{-1} B the normal-equations matrix of the
+ * ADMM x-step (eq. (3.9), in the psi-scaled form B = psi D).  No aliasing. */
+fde_status fde_apply_S(fde_ctx* ctx, const double* x, double* y);
+
+/* z = S~^{-1} r, the Schur-complement approximation of eq. (3.10) built
+ * from the 3-level T. Chan circulant of eq. (5.2): 3-D real FFT, division by
+ * the eigenvalues a + |psi (lt - ly - lx)|^2 / mbar_p, inverse FFT.  Runs in
+ * float32 when the problem asked for it.  r and z may alias. */
+fde_status fde_precond(fde_ctx* ctx, const double* r, double* z);
+
+/* Solve S x = b by PCG with S~ (Sec. 6.1 uses PCG on eq. (3.9)), Fletcher-
+ * Reeves beta, stopping when the recursively updated ||r||_2 <= krylov_tol
+ * ||b||_2.  x holds the initial guess on entry and the solution on exit.
+ * *iters (host) receives the iteration count, *relres (host) the final
+ * relative residual.  Synchronises the stream.  FDE_ENOTCONV after
+ * krylov_maxit iterations. */
+fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, double* relres);
+
+/* Algorithm 1 (2-block ADMM, Sec. 3.1) with the merged x-step: the normal
+ * equations solved by fde_krylov's PCG, the z-step as the box projection,
+ * the dual updates, and the stopping test of Sec. 6.1 on the scaled primal
+ * residual and the two copy residuals.  yhat: desired state; g: FDE right-
+ * hand side (NULL = 0).  y, u, zy, zu, p, wy, wu are the ADMM iterates
+ * (p the scaled multiplier of B y + k_u u = psi g, wy/wu those of the copy
+ * constraints): read as the starting point (all zeros for a cold start; a
+ * previous call's outputs to resume) and overwritten with the last iterate.
+ * *stats (host, may be NULL) receives counts and residuals.  Synchronises. */
+fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, double* y, double* u,
+                          double* zy, double* zu, double* p, double* wy, double* wu,
+                          fde_admm_stats* stats);
+
+/* Gradients of the optimal value J*(yhat, alpha, beta) at an ADMM solution
+ * (envelope theorem on the Lagrangian of eq. (3.5)):
+ *   dJ/dyhat = -J1 (y - yhat)                       -> dyhat (device field)
+ *   dJ/dalpha = lambda^T (dD/dalpha) y, dJ/dbeta likewise -> dab[2] (host)
+ * lambda is obtained by the adjoint solve D^T lambda = -J1 (y - yhat) - wy
+ * (backward time stepping of the transposed operator, whose Toeplitz
+ * products use the reversed weights; each step by preconditioned Krylov),
+ * when adjoint_solve = 1, or taken as psi * p when adjoint_solve = 0.
+ * dD/dalpha uses the derivative of the Grünwald recurrence.  lambda_out
+ * (device field, may be NULL) receives lambda.  Synchronises. */
+fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const double* p,
+                    const double* wy, int adjoint_solve, double* dyhat, double* dab,
+                    double* lambda_out);
+
+/* Last error message of the calling thread ("" if none). */
+const char* fde_last_error(void);
+
+/* Library version string. */
+const char* fde_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDE_H */

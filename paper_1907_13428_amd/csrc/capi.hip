@@ -1,0 +1,663 @@
+// C ABI of the FDE-constrained ADMM hot path (declared in include/fde.h).
+//
+// Host control, device work: every step of the Krylov and ADMM iterations
+// runs in the kernels of k_toeplitz.hip, k_precond.hip and k_vector.hip.
+// Scalars of the iteration (alpha, beta, residual norms, the convergence
+// flag) stay in device memory; the host enqueues PCG iterations in chunks
+// whose kernels exit at once after the device-side convergence flag is set,
+// and reads the flag back once per chunk.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fde_internal.hpp"
+#include "host_setup.hpp"
+
+using fde::host::cd;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      return (fde_status)fail(FDE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+struct fde_ctx {
+  fde_problem prob{};
+  fde_admm_params prm{};
+  fde::host::Setup su;
+  hipStream_t stream = nullptr;
+  int nx = 0, ny = 0, nt = 0, H = 0;
+  int64_t N = 0;
+  bool var = false, fp32 = false;
+
+  // device tables
+  double2 *lxA = nullptr, *lxB = nullptr, *lxTA = nullptr, *lxTB = nullptr;  // x: fwd (A,B), trans (A,B)
+  double2 *lyA = nullptr, *lyB = nullptr, *lyTA = nullptr, *lyTB = nullptr;
+  double2 *twx_emb = nullptr, *twy_emb = nullptr;
+  void *twx = nullptr, *twy = nullptr, *twt = nullptr;
+  double2 *tcx = nullptr, *tcy = nullptr, *tct = nullptr;
+  double *dplus = nullptr, *dminus = nullptr;
+  double *invMp = nullptr, *My = nullptr, *Mu = nullptr, *Mp = nullptr, *wts = nullptr, *ones = nullptr;
+  double2 *dxA = nullptr, *dxB = nullptr, *dyA = nullptr, *dyB = nullptr;  // dL/dalpha, dL/dbeta
+
+  // workspace fields
+  double *fa = nullptr, *fw = nullptr, *fb = nullptr;  // line-pass intermediates
+  double *q = nullptr, *r = nullptr, *z = nullptr, *pk = nullptr, *bvec = nullptr;
+  double *ar = nullptr, *Ru = nullptr, *av = nullptr, *ac = nullptr, *By = nullptr;
+  void* spec = nullptr;
+  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_max = nullptr;
+  int maxpart = 0;
+  double* scal = nullptr;
+  int* ints = nullptr;
+  double* h_scal = nullptr;  // pinned
+  int* h_ints = nullptr;
+  std::vector<void*> allocs;
+
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, count * sizeof(T));
+    if (e == hipSuccess) {
+      allocs.push_back(v);
+      *p = static_cast<T*>(v);
+    }
+    return e;
+  }
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload(fde_ctx* c, T** dst, const std::vector<T>& src) {
+  hipError_t e = c->alloc(dst, src.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+hipError_t upload_c(fde_ctx* c, double2** dst, const std::vector<cd>& src) {
+  std::vector<double2> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = double2{src[i].real(), src[i].imag()};
+  return upload(c, dst, tmp);
+}
+
+hipError_t upload_tw(fde_ctx* c, void** dst, const std::vector<cd>& src, bool fp32) {
+  if (fp32) {
+    std::vector<float2> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = float2{(float)src[i].real(), (float)src[i].imag()};
+    float2* d = nullptr;
+    hipError_t e = upload(c, &d, tmp);
+    *dst = d;
+    return e;
+  }
+  double2* d = nullptr;
+  hipError_t e = upload_c(c, &d, src);
+  *dst = d;
+  return e;
+}
+
+// maximum number of blocks any reducing launch uses (partial-sum capacity)
+int max_partials(int nx, int ny, int nt) {
+  const long long N = (long long)nx * ny * nt;
+  long long m = 2048;  // vector kernels
+  // y-pass: tiles * nt with at least 2 columns per tile
+  m = std::max(m, (long long)((nx + 1) / 2) * nt);
+  // x-inverse of the preconditioner: pairs of lines, at least one pair per block
+  m = std::max(m, (long long)(ny * nt + 1) / 2);
+  (void)N;
+  return (int)m;
+}
+
+fde::LinePassArgs line_args(fde_ctx* c) {
+  fde::LinePassArgs a{};
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nt = c->nt;
+  a.dplus = c->dplus;
+  a.dminus = c->dminus;
+  return a;
+}
+
+// x-pass: out = s_time * (E or E^T) in + s_sp * L_x(^T) in
+hipError_t xpass(fde_ctx* c, const double* in, double* out, bool tr, double s_time, double s_sp,
+                 const int* done) {
+  fde::LinePassArgs a = line_args(c);
+  a.in = in;
+  a.out = out;
+  a.tw = c->twx_emb;
+  if (c->var) {
+    a.lamA = tr ? c->lxTA : c->lxA;
+    a.lamB = tr ? c->lxTB : c->lxB;
+  } else {
+    a.lamA = tr ? c->lxTA : c->lxA;
+  }
+  a.s_time = s_time;
+  a.s_sp = s_sp;
+  a.done = done;
+  return fde::launch_xpass(a, tr, c->var, c->stream, nullptr);
+}
+
+// y-pass: out_t = osc[t] (acc + s_sp L_y(^T) in) + esc[t] extra
+hipError_t ypass(fde_ctx* c, const double* in, const double* acc, double* out, bool tr, double s_sp,
+                 const double* osc, const double* extra, const double* esc, const double* dotv,
+                 double* partial, const int* done, int* nb) {
+  fde::LinePassArgs a = line_args(c);
+  a.in = in;
+  a.out = out;
+  a.tw = c->twy_emb;
+  a.lamA = tr ? c->lyTA : c->lyA;
+  a.lamB = tr ? c->lyTB : c->lyB;
+  a.s_sp = s_sp;
+  a.acc = acc;
+  a.oscale = osc;
+  a.extra = extra;
+  a.escale = esc;
+  a.dotv = dotv;
+  a.partial = partial;
+  a.done = done;
+  return fde::launch_ypass(a, tr, c->var, c->stream, nb);
+}
+
+// y = S x = M_y x + B^T M_p^{-1} B x, optional partial sums of (x, y)
+hipError_t apply_S(fde_ctx* c, const double* x, double* y, double* partial, const int* done, int* nb) {
+  const double psi = c->su.psi, sti = psi / c->su.ht;
+  hipError_t e;
+  if ((e = xpass(c, x, c->fa, false, sti, -psi, done)) != hipSuccess) return e;
+  if ((e = ypass(c, x, c->fa, c->fw, false, -psi, c->invMp, nullptr, nullptr, nullptr, nullptr, done,
+                 nullptr)) != hipSuccess)
+    return e;
+  if ((e = xpass(c, c->fw, c->fb, true, sti, -psi, done)) != hipSuccess) return e;
+  return ypass(c, c->fw, c->fb, y, true, -psi, nullptr, x, c->My, partial ? x : nullptr, partial, done, nb);
+}
+
+fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
+  fde::PrecondArgs a{};
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nt = c->nt;
+  a.H = c->H;
+  a.r = r;
+  a.z = z;
+  a.spec = c->spec;
+  a.twx = c->twx;
+  a.twy = c->twy;
+  a.twt = c->twt;
+  a.lam_x = c->tcx;
+  a.lam_y = c->tcy;
+  a.lam_t = c->tct;
+  a.psi = c->su.psi;
+  a.a = c->su.a;
+  a.inv_mbar = c->su.inv_mbar;
+  a.inv_n = 1.0 / (double)c->N;
+  a.scal = c->scal;
+  return a;
+}
+
+fde_status check_ctx(fde_ctx* c) {
+  if (!c) return (fde_status)fail(FDE_EINVAL, "context is NULL");
+  return FDE_OK;
+}
+
+fde_status sync_scalars(fde_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * fde::kNumScalars, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->h_ints, c->ints, sizeof(int) * fde::kNumInts, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FDE_OK;
+}
+
+// PCG on S x = b (x: initial guess in, solution out).  Returns status; fills iters/relres.
+fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit, int* iters, double* relres,
+                  int predict) {
+  using namespace fde;
+  const int* done = c->ints + kDone;
+  // tolerance and iteration limit into device scalars
+  const double tol2 = tol * tol;
+  int nbS = 0, nbv = 0, nb1 = 0, nb5 = 0;
+  // r = b - S x ; (r, r), (b, b)
+  HIP_TRY(apply_S(c, x, c->q, nullptr, nullptr, nullptr));
+  HIP_TRY(launch_axpy_dot(VEC_RESID, c->N, b, c->q, c->r, c->scal, c->part_pq, nullptr, c->stream, &nbv));
+  HIP_TRY(launch_pcg_scalar(FIN_INIT, c->part_pq, nbv, c->scal, c->ints, c->stream, tol2, maxit));
+  HIP_TRY(launch_axpy_dot(VEC_ZERO_IF_BB0, c->N, nullptr, nullptr, x, c->scal, nullptr, nullptr, c->stream,
+                          nullptr));
+  // z = S~^{-1} r ; p = z ; rz = (r, z)
+  {
+    PrecondArgs a = pre_args(c, c->r, c->z);
+    a.partial2 = c->part_rz;
+    a.done = done;
+    HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
+    HIP_TRY(launch_pcg_scalar(FIN_RZ0, c->part_rz, nb5, c->scal, c->ints, c->stream));
+    HIP_TRY(launch_axpy_dot(VEC_COPY, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr));
+  }
+  int enqueued = 0;
+  int chunk = predict > 1 ? predict : 2;
+  fde_status st = FDE_OK;
+  while (true) {
+    for (int k = 0; k < chunk && enqueued < maxit; ++k, ++enqueued) {
+      // q = S p ; alpha = (r,z)/(p,q)
+      HIP_TRY(apply_S(c, c->pk, c->q, c->part_pq, done, &nbS));
+      HIP_TRY(launch_pcg_scalar(FIN_ALPHA, c->part_pq, nbS, c->scal, c->ints, c->stream));
+      // x += alpha p ; r -= alpha q ; (r, r) ; convergence test ; z = S~^{-1} r ; (r, z) ; beta
+      PrecondArgs a = pre_args(c, c->r, c->z);
+      a.q = c->q;
+      a.xvec = x;
+      a.pvec = c->pk;
+      a.partial = c->part_rr;
+      a.partial2 = c->part_rz;
+      a.done = done;
+      HIP_TRY(launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5));
+      HIP_TRY(launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream));
+      HIP_TRY(launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5));
+      HIP_TRY(launch_pcg_scalar(FIN_BETA, c->part_rz, nb5, c->scal, c->ints, c->stream));
+      // p = z + beta p
+      HIP_TRY(launch_axpy_dot(VEC_PUPDATE, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream,
+                              nullptr));
+    }
+    if ((st = sync_scalars(c)) != FDE_OK) return st;
+    if (c->h_ints[kDone] || enqueued >= maxit) break;
+    chunk = 2;
+  }
+  *iters = c->h_ints[kIter];
+  const double bb = c->h_scal[kBB];
+  *relres = bb > 0 ? std::sqrt(c->h_scal[kRR] / bb) : 0.0;
+  if (c->h_ints[kConv] < 0) return (fde_status)fail(FDE_ENONFINITE, "non-finite residual in PCG");
+  if (c->h_ints[kConv] == 0) return FDE_ENOTCONV;
+  return FDE_OK;
+}
+
+fde_status free_all(fde_ctx* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  if (c->h_ints) (void)hipHostFree(c->h_ints);
+  c->h_scal = nullptr;
+  c->h_ints = nullptr;
+  return FDE_OK;
+}
+
+fde_status upload_admm_tables(fde_ctx* c) {
+  const auto& s = c->su;
+  const size_t bytes = sizeof(double) * c->nt;
+  HIP_TRY(hipMemcpy(c->invMp, s.invMp.data(), bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->My, s.My.data(), bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->Mu, s.Mu.data(), bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->Mp, s.Mp.data(), bytes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->wts, s.wts.data(), bytes, hipMemcpyHostToDevice));
+  return FDE_OK;
+}
+
+// D^T lambda = -J1 (y - yhat) - wy  (adjoint state equation)
+fde_status adjoint_solve_impl(fde_ctx* c, const double* yhat, const double* y, const double* wy, double* lam) {
+  (void)c; (void)yhat; (void)y; (void)wy; (void)lam;
+  return (fde_status)fail(FDE_EINVAL, "fde_grad: adjoint_solve = 1 is not available in this build");
+}
+
+fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void* stream, fde_ctx** out) {
+  if (!out) return (fde_status)fail(FDE_EINVAL, "out is NULL");
+  *out = nullptr;
+  auto* c = new fde_ctx();
+  std::string msg;
+  int st = fde::host::build_setup(prob, prm, &c->su, &msg);
+  if (st != FDE_OK) {
+    delete c;
+    return (fde_status)fail(st, msg);
+  }
+  c->prob = *prob;
+  c->prob.dplus = nullptr;
+  c->prob.dminus = nullptr;
+  c->prm = *prm;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->nx = prob->nx;
+  c->ny = prob->ny;
+  c->nt = prob->nt;
+  c->H = prob->nx / 2 + 1;
+  c->N = (int64_t)prob->nx * prob->ny * prob->nt;
+  c->var = c->su.var;
+  c->fp32 = prob->precond_fp32 != 0;
+  auto& s = c->su;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess && x != hipSuccess) e = x;
+  };
+  // operator tables (x: length 2nx, y: 2ny)
+  if (c->var) {
+    chk(upload_c(c, &c->lxA, s.x.lamG));
+    chk(upload_c(c, &c->lxB, s.x.lamGT));
+    chk(upload_c(c, &c->lxTA, s.x.lamGT));  // transpose: G^T (d+ v) + G (d- v)
+    chk(upload_c(c, &c->lxTB, s.x.lamG));
+    chk(upload_c(c, &c->lyA, s.y.lamG));
+    chk(upload_c(c, &c->lyB, s.y.lamGT));
+    chk(upload_c(c, &c->lyTA, s.y.lamGT));
+    chk(upload_c(c, &c->lyTB, s.y.lamG));
+    chk(upload(c, &c->dplus, s.dplus));
+    chk(upload(c, &c->dminus, s.dminus));
+  } else {
+    chk(upload_c(c, &c->lxA, s.x.lamFwd));
+    chk(upload_c(c, &c->lxTA, s.x.lamTr));
+    chk(upload_c(c, &c->lyA, s.y.lamFwd));
+    chk(upload_c(c, &c->lyTA, s.y.lamTr));
+  }
+  chk(upload_c(c, &c->dxA, s.x.dopA));
+  chk(upload_c(c, &c->dxB, s.x.dopB));
+  chk(upload_c(c, &c->dyA, s.y.dopA));
+  chk(upload_c(c, &c->dyB, s.y.dopB));
+  chk(upload_c(c, &c->twx_emb, s.x.tw_emb));
+  chk(upload_c(c, &c->twy_emb, s.y.tw_emb));
+  chk(upload_tw(c, &c->twx, s.x.tw, c->fp32));
+  chk(upload_tw(c, &c->twy, s.y.tw, c->fp32));
+  chk(upload_tw(c, &c->twt, s.tw_t, c->fp32));
+  chk(upload_c(c, &c->tcx, s.x.tchan));
+  chk(upload_c(c, &c->tcy, s.y.tchan));
+  chk(upload_c(c, &c->tct, s.tchan_t));
+  chk(c->alloc(&c->invMp, c->nt));
+  chk(c->alloc(&c->My, c->nt));
+  chk(c->alloc(&c->Mu, c->nt));
+  chk(c->alloc(&c->Mp, c->nt));
+  chk(c->alloc(&c->wts, c->nt));
+  chk(upload(c, &c->ones, std::vector<double>(c->nt, 1.0)));
+  // workspace
+  const size_t N = (size_t)c->N;
+  double** fields[] = {&c->fa, &c->fw, &c->fb, &c->q, &c->r, &c->z, &c->pk, &c->bvec,
+                       &c->ar, &c->Ru, &c->av, &c->ac, &c->By};
+  for (double** f : fields) chk(c->alloc(f, N));
+  const size_t specn = (size_t)c->H * c->ny * c->nt;
+  if (c->fp32) {
+    float2* sp = nullptr;
+    chk(c->alloc(&sp, specn));
+    c->spec = sp;
+  } else {
+    double2* sp = nullptr;
+    chk(c->alloc(&sp, specn));
+    c->spec = sp;
+  }
+  c->maxpart = max_partials(c->nx, c->ny, c->nt);
+  chk(c->alloc(&c->part_pq, 2 * (size_t)c->maxpart));
+  chk(c->alloc(&c->part_rr, (size_t)c->maxpart));
+  chk(c->alloc(&c->part_rz, (size_t)c->maxpart));
+  chk(c->alloc(&c->part_max, 3 * (size_t)c->maxpart));
+  chk(c->alloc(&c->scal, fde::kNumScalars));
+  chk(c->alloc(&c->ints, fde::kNumInts));
+  if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_scal, sizeof(double) * fde::kNumScalars, hipHostMallocDefault));
+  if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_ints, sizeof(int) * fde::kNumInts, hipHostMallocDefault));
+  if (e == hipSuccess) chk(hipMemset(c->scal, 0, sizeof(double) * fde::kNumScalars));
+  if (e == hipSuccess) chk(hipMemset(c->ints, 0, sizeof(int) * fde::kNumInts));
+  if (e != hipSuccess) {
+    const int code = (e == hipErrorOutOfMemory) ? FDE_ENOMEM : FDE_EHIP;
+    free_all(c);
+    delete c;
+    return (fde_status)fail(code, std::string("fde_create: ") + hipGetErrorString(e));
+  }
+  fde_status us = upload_admm_tables(c);
+  if (us != FDE_OK) {
+    free_all(c);
+    delete c;
+    return us;
+  }
+  *out = c;
+  return FDE_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* fde_last_error(void) { return g_err.c_str(); }
+
+const char* fde_version(void) { return "fde-mi355x 0.1 (gfx950)"; }
+
+fde_status fde_validate(const fde_problem* prob, const fde_admm_params* prm) {
+  std::string msg;
+  const int st = fde::host::validate(prob, prm, &msg);
+  if (st != FDE_OK) return (fde_status)fail(st, msg);
+  g_err.clear();
+  return FDE_OK;
+}
+
+fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, double* scal, double* lam_x,
+                           double* lam_y, double* lam_t, double* gx, double* gy) {
+  fde::host::Setup s;
+  std::string msg;
+  const int st = fde::host::build_setup(prob, prm, &s, &msg);
+  if (st != FDE_OK) return (fde_status)fail(st, msg);
+  if (scal) {
+    const double v[8] = {s.psi, s.x.h, s.y.h, s.ht, s.a, s.inv_mbar, s.e_u, s.k_u};
+    std::memcpy(scal, v, sizeof v);
+  }
+  auto put = [](double* dst, const std::vector<cd>& src) {
+    if (!dst) return;
+    for (size_t i = 0; i < src.size(); ++i) {
+      dst[2 * i] = src[i].real();
+      dst[2 * i + 1] = src[i].imag();
+    }
+  };
+  put(lam_x, s.x.tchan);
+  put(lam_y, s.y.tchan);
+  put(lam_t, s.tchan_t);
+  if (gx) std::memcpy(gx, s.x.g.data(), sizeof(double) * s.x.g.size());
+  if (gy) std::memcpy(gy, s.y.g.data(), sizeof(double) * s.y.g.size());
+  return FDE_OK;
+}
+
+fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream, fde_ctx** out) {
+  return create_impl(prob, prm, stream, out);
+}
+
+fde_status fde_destroy(fde_ctx* ctx) {
+  if (!ctx) return FDE_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  delete ctx;
+  return FDE_OK;
+}
+
+fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  std::string msg;
+  const int st = fde::host::validate_params(prm, &msg);
+  if (st != FDE_OK) return (fde_status)fail(st, msg);
+  ctx->prm = *prm;
+  fde::host::set_admm_scalings(prm, &ctx->su);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return upload_admm_tables(ctx);
+}
+
+fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_A: null or aliased fields");
+  const bool tr = transpose != 0;
+  const double sti = 1.0 / ctx->su.ht;
+  HIP_TRY(xpass(ctx, x, ctx->fa, tr, sti, -1.0, nullptr));
+  HIP_TRY(ypass(ctx, x, ctx->fa, y, tr, -1.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+  return FDE_OK;
+}
+
+fde_status fde_apply_S(fde_ctx* ctx, const double* x, double* y) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_S: null or aliased fields");
+  HIP_TRY(apply_S(ctx, x, y, nullptr, nullptr, nullptr));
+  return FDE_OK;
+}
+
+fde_status fde_precond(fde_ctx* ctx, const double* r, double* z) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!r || !z) return (fde_status)fail(FDE_EINVAL, "fde_precond: null field");
+  fde::PrecondArgs a = pre_args(ctx, const_cast<double*>(r), z);  // r is only read (no fused update)
+  HIP_TRY(fde::launch_precond(a, ctx->fp32, ctx->stream, nullptr, nullptr));
+  return FDE_OK;
+}
+
+fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, double* relres) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!b || !x || b == x) return (fde_status)fail(FDE_EINVAL, "fde_krylov: null or aliased fields");
+  int it = 0;
+  double rr = 0;
+  const fde_status st = krylov(ctx, b, x, ctx->prm.krylov_tol, ctx->prm.krylov_maxit, &it, &rr, 0);
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return st;
+}
+
+fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, double* y, double* u, double* zy,
+                          double* zu, double* p, double* wy, double* wu, fde_admm_stats* stats) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!yhat || !y || !u || !zy || !zu || !p || !wy || !wu)
+    return (fde_status)fail(FDE_EINVAL, "fde_admm_solve: null field");
+  fde_ctx* c = ctx;
+  const auto& s = c->su;
+  const fde_admm_params& q = c->prm;
+  const double t0 = now();
+  double t_pcg = 0.0;
+  fde::AdmmConsts k{};
+  k.n = c->N;
+  k.plane = c->nx * c->ny;
+  k.nt = c->nt;
+  k.rho = q.rho;
+  k.delta = q.delta;
+  k.e_y = s.e_y;
+  k.e_u = s.e_u;
+  k.k_u = s.k_u;
+  k.ya = q.ya;
+  k.yb = q.yb;
+  k.ua = q.ua;
+  k.ub = q.ub;
+  k.wts = c->wts;
+  k.Mu = c->Mu;
+  k.Mp = c->Mp;
+  fde::AdmmFields f{};
+  f.yhat = yhat;
+  f.g = g;
+  f.y = y;
+  f.u = u;
+  f.zy = zy;
+  f.zu = zu;
+  f.p = p;
+  f.wy = wy;
+  f.wu = wu;
+  f.r = c->ar;
+  f.Ru = c->Ru;
+  f.v = c->av;
+  f.c = c->ac;
+  f.By = c->By;
+  f.partial = c->part_max;
+  const double psi = s.psi, sti = psi / s.ht;
+  fde_admm_stats st{};
+  fde_status status = FDE_ENOTCONV;
+  double prev_min = 0.0;
+  int predict = 0;
+  for (int j = 1; j <= q.admm_maxit; ++j) {
+    // 1. right-hand side b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
+    HIP_TRY(fde::launch_admm_rhs(k, f, psi, c->stream));
+    HIP_TRY(xpass(c, c->av, c->fb, true, sti, -psi, nullptr));
+    HIP_TRY(ypass(c, c->av, c->fb, c->bvec, true, -psi, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr,
+                  nullptr));
+    // 2. S y = b by PCG, warm-started from the previous y
+    const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(prev_min, 1e-4) : q.krylov_tol;
+    int it = 0;
+    double rel = 0;
+    const double tp = now();
+    const fde_status ks = krylov(c, c->bvec, y, tol, q.krylov_maxit, &it, &rel, predict);
+    t_pcg += now() - tp;
+    if (ks < 0) return ks;
+    predict = it > 2 ? it - 1 : 2;
+    st.pcg_total += it;
+    st.pcg_last = it;
+    if (it > st.pcg_max) st.pcg_max = it;
+    // 3-5. By ; p, u recovery ; projection ; dual updates ; residual maxima
+    HIP_TRY(xpass(c, y, c->fa, false, sti, -psi, nullptr));
+    HIP_TRY(ypass(c, y, c->fa, c->By, false, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  nullptr));
+    int nb = 0;
+    HIP_TRY(fde::launch_admm_update(k, f, psi, c->stream, &nb));
+    HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
+    fde_status ss = sync_scalars(c);
+    if (ss != FDE_OK) return ss;
+    st.admm_iters = j;
+    st.r_p = c->h_scal[fde::kResP];
+    st.r_y = c->h_scal[fde::kResY];
+    st.r_u = c->h_scal[fde::kResU];
+    if (std::isnan(st.r_p) || std::isnan(st.r_y) || std::isnan(st.r_u)) {
+      status = (fde_status)fail(FDE_ENONFINITE, "non-finite ADMM residual");
+      break;
+    }
+    prev_min = std::fmin(st.r_p, std::fmin(st.r_y, st.r_u));
+    // 6. termination (Sec. 6.1)
+    if (q.admm_tol > 0 && std::fmax(st.r_p, std::fmax(st.r_y, st.r_u)) <= q.admm_tol) {
+      status = FDE_OK;
+      break;
+    }
+  }
+  st.t_total = now() - t0;
+  st.t_pcg = t_pcg;
+  if (stats) *stats = st;
+  return status;
+}
+
+fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const double* p, const double* wy,
+                    int adjoint_solve, double* dyhat, double* dab, double* lambda_out) {
+  using namespace fde;
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!yhat || !y || !p || !dab) return (fde_status)fail(FDE_EINVAL, "fde_grad: null argument");
+  fde_ctx* c = ctx;
+  double* lam = lambda_out ? lambda_out : c->z;
+  if (adjoint_solve) {
+    if (!wy) return (fde_status)fail(FDE_EINVAL, "fde_grad: the adjoint solve needs wy");
+    const fde_status st = adjoint_solve_impl(c, yhat, y, wy, lam);
+    if (st < 0) return st;
+    HIP_TRY(launch_grad_fields(c->N, c->nx * c->ny, c->wts, y, yhat, p, c->su.psi, dyhat, nullptr, c->stream));
+  } else {
+    HIP_TRY(launch_grad_fields(c->N, c->nx * c->ny, c->wts, y, yhat, p, c->su.psi, dyhat, lam, c->stream));
+  }
+  // dJ/dalpha = -lambda^T (dL_x/dalpha) y ; dJ/dbeta = -lambda^T (dL_y/dbeta) y
+  fde::LinePassArgs a = line_args(c);
+  a.in = y;
+  a.out = c->fa;
+  a.tw = c->twx_emb;
+  a.lamA = c->dxA;
+  a.lamB = c->dxB;
+  a.s_time = 0.0;
+  a.s_sp = 1.0;
+  HIP_TRY(launch_xpass(a, false, c->var, c->stream, nullptr));
+  fde::LinePassArgs b = line_args(c);
+  b.in = y;
+  b.out = c->fb;
+  b.tw = c->twy_emb;
+  b.lamA = c->dyA;
+  b.lamB = c->dyB;
+  b.s_sp = 1.0;
+  HIP_TRY(launch_ypass(b, false, c->var, c->stream, nullptr));
+  double out[2];
+  const double* fld[2] = {c->fa, c->fb};
+  for (int i = 0; i < 2; ++i) {
+    int nb = 0;
+    HIP_TRY(launch_axpy_dot(VEC_DOT, c->N, lam, fld[i], nullptr, c->scal, c->part_pq, nullptr, c->stream, &nb));
+    HIP_TRY(launch_pcg_scalar(FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
+    const fde_status ss = sync_scalars(c);
+    if (ss != FDE_OK) return ss;
+    out[i] = -c->h_scal[kDot];
+  }
+  dab[0] = out[0];
+  dab[1] = out[1];
+  return FDE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal declarations shared by the host code and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fde.h"
+
+namespace fde {
+
+constexpr int kBlock = 256;        // threads per block of the elementwise / reduction kernels
+constexpr int kMaxPartials = 4096;  // partial-sum slots per reduction
+
+// ---------------------------------------------------------------------------
+// Toeplitz line passes (operator D and D^T)
+//
+//   x-pass:  out = s_time * (E or E^T) in + s_sp * (L_x or L_x^T) in
+//   y-pass:  out_t = oscale[t] * (acc + s_sp * (L_y or L_y^T) in) + escale[t] * extra
+//            (+ optional partial sums of dotv * out)
+// E is the implicit-Euler time difference (v_t - v_{t-1}) / h_t, E^T uses
+// v_{t+1}.  The spatial operators are (c_a/h^a)(diag(d+) G + diag(d-) G^T)
+// applied by a 2n circulant embedding; the eigenvalue tables already carry
+// c_a/h^a and the 1/(2n) of the inverse transform.
+// ---------------------------------------------------------------------------
+struct LinePassArgs {
+  const double* in;
+  double* out;
+  int nx, ny, nt;
+  // spectral multipliers of the embedding circulants (length 2n, complex)
+  const double2* lamA;  // constant coefficients: combined operator; variable: G
+  const double2* lamB;  // variable coefficients: G^T (unused otherwise)
+  const double2* tw;    // twiddles of length 2n
+  const double* dplus;  // (ny, nx) or nullptr for constant coefficients
+  const double* dminus;
+  double s_time;  // x-pass only: coefficient of the time difference
+  double s_sp;    // coefficient of the spatial operator
+  // y-pass epilogue
+  const double* acc;     // may be nullptr
+  const double* oscale;  // per time slice, may be nullptr (= 1)
+  const double* extra;   // may be nullptr
+  const double* escale;  // per time slice
+  const double* dotv;    // may be nullptr: then no partial sums
+  double* partial;       // one slot per block
+  const int* done;       // early-exit flag (may be nullptr)
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_xpass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
+hipError_t launch_ypass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
+bool fft_length_supported(int L);
+
+// ---------------------------------------------------------------------------
+// preconditioner passes: z = S~^{-1} r via a 3-D real FFT
+// ---------------------------------------------------------------------------
+struct PrecondArgs {
+  int nx, ny, nt, H;  // H = nx/2 + 1 complex columns of the half spectrum
+  double* r;          // input field (updated in place by the fused x-forward pass)
+  double* z;          // output field
+  void* spec;         // half spectrum [nt][ny][H], double2 or float2
+  const void* twx;    // twiddles (length nx, ny, nt) in the spectrum precision
+  const void* twy;
+  const void* twt;
+  const double2* lam_x;  // T. Chan eigenvalues (FP64 always)
+  const double2* lam_y;
+  const double2* lam_t;
+  double psi, a, inv_mbar, inv_n;  // s = a + |psi (lt - ly - lx)|^2 * inv_mbar; 1/(nx ny nt)
+  // fused PCG pieces
+  const double* q;        // x-forward: r -= alpha q (if non-null)
+  double* xvec;           // x-forward: x += alpha p
+  const double* pvec;
+  const double* scal;     // device scalars (alpha at index kAlpha)
+  double* partial;        // x-forward: partial sums of r.r (fused mode only)
+  double* partial2;       // x-inverse: partial sums of r.z (nullptr: none)
+  const int* done;
+};
+
+// stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5
+hipError_t launch_precond_stage(const PrecondArgs& a, bool fp32, int stage, hipStream_t s, int* nb_fwd,
+                                int* nb_inv);
+inline hipError_t launch_precond(const PrecondArgs& a, bool fp32, hipStream_t s, int* nb_fwd, int* nb_inv) {
+  return launch_precond_stage(a, fp32, 0, s, nb_fwd, nb_inv);
+}
+
+// ---------------------------------------------------------------------------
+// device scalar slots of the Krylov / ADMM state
+// ---------------------------------------------------------------------------
+enum ScalarSlot {
+  kRZ = 0,    // (r, z)
+  kPQ,        // (p, q)
+  kAlpha,
+  kBeta,
+  kRR,        // (r, r)
+  kBB,        // (b, b)
+  kTol2,      // tol^2
+  kResP,      // ADMM residuals
+  kResY,
+  kResU,
+  kDot,       // scratch dot result
+  kNumScalars
+};
+enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kNumInts };
+
+// elementwise / reduction kernels
+enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_ALPHA, FIN_CONV, FIN_BETA, FIN_DOT };
+enum VecOp {
+  VEC_RESID = 0,    // c = a - b ; partials (c,c) and (a,a)
+  VEC_PUPDATE,      // c = a + beta c
+  VEC_COPY,         // c = a
+  VEC_DOT,          // partial (a, b)
+  VEC_ZERO_IF_BB0,  // c = 0 when scal[kBB] == 0
+  VEC_SCALE         // c = scal[kDot] * a  (scalar taken from the device slot)
+};
+// FIN_INIT also stores tol2 and maxit in the device slots
+hipError_t launch_pcg_scalar(int op, const double* partial, int n, double* scal, int* ints, hipStream_t s,
+                             double tol2 = 0.0, int maxit = 0);
+hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, double* c,
+                           const double* scal, double* partial, const int* done, hipStream_t s,
+                           int* nblocks);
+
+struct AdmmConsts {
+  int64_t n;
+  int plane;  // nx * ny
+  int nt;
+  double rho, delta, e_y, e_u, k_u, ya, yb, ua, ub;
+  const double* wts;  // per time slice J1 diagonal
+  const double* Mu;   // per time slice
+  const double* Mp;
+};
+struct AdmmFields {
+  const double* yhat;
+  const double* g;  // may be null
+  double *y, *u, *zy, *zu, *p, *wy, *wu;
+  double *r, *Ru, *v, *c, *By;
+  double* partial;  // 3 * blocks
+};
+hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s);
+hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
+                              int* nblocks);
+hipError_t launch_max3_finalize(const double* partial, int nblocks, double* scal, hipStream_t s);
+// gradient pieces: dyhat = -J1 (y - yhat), lam = psi p
+hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
+                              const double* p, double psi, double* dyhat, double* lam, hipStream_t s);
+
+}  // namespace fde

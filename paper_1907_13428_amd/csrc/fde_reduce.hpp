@@ -1,0 +1,48 @@
+// Deterministic block reductions (fixed order for a fixed launch shape).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fde {
+
+// Sum over the block; the result is valid in thread 0.  All threads must call.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "block must be whole wavefronts");
+  __shared__ double ws[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += ws[w];
+  }
+  return s;
+}
+
+// NaN-propagating max of non-negative values
+__device__ __forceinline__ double nanmax(double a, double b) {
+  return (b > a || b != b) ? b : a;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double wm[NT / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) wm[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s = nanmax(s, wm[w]);
+  }
+  return s;
+}
+
+}  // namespace fde

@@ -1,0 +1,285 @@
+// Host-side setup (see host_setup.hpp).
+#include "host_setup.hpp"
+
+#include <cmath>
+#include <cstdio>
+
+namespace fde {
+namespace host {
+
+namespace {
+const double kPi = 3.14159265358979323846264338327950288;
+
+bool finite(double v) { return std::isfinite(v); }
+
+std::string fmt(const char* f, double a) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, f, a);
+  return buf;
+}
+}  // namespace
+
+bool length_supported(int n) {
+  // n = 2^a 3^b with b <= 1 and 4 <= n <= 1024 (FFT radices 2/4/8 and one 3)
+  if (n < 4 || n > 1024) return false;
+  int m = n;
+  if (m % 3 == 0) m /= 3;
+  while (m % 2 == 0) m /= 2;
+  return m == 1;
+}
+
+int validate_params(const fde_admm_params* q, std::string* msg) {
+  if (!q) { *msg = "params is NULL"; return FDE_EINVAL; }
+  if (!(q->gamma > 0) || !finite(q->gamma)) { *msg = "gamma must be finite and > 0"; return FDE_EINVAL; }
+  if (!(q->delta > 0) || !finite(q->delta)) { *msg = "delta must be finite and > 0"; return FDE_EINVAL; }
+  const double rmax = 0.5 * (1.0 + std::sqrt(5.0));
+  if (!(q->rho > 0 && q->rho < rmax)) { *msg = "rho must lie in (0, (1+sqrt5)/2)"; return FDE_EINVAL; }
+  if (std::isnan(q->ya) || std::isnan(q->yb) || std::isnan(q->ua) || std::isnan(q->ub)) {
+    *msg = "bounds must not be NaN";
+    return FDE_EINVAL;
+  }
+  if (q->ya > q->yb || q->ua > q->ub) { *msg = "lower bound exceeds upper bound"; return FDE_EINVAL; }
+  if (q->ya == INFINITY || q->yb == -INFINITY || q->ua == INFINITY || q->ub == -INFINITY) {
+    *msg = "empty box (infinite bound on the wrong side)";
+    return FDE_EINVAL;
+  }
+  if (!(q->krylov_tol >= 0) || !finite(q->krylov_tol)) { *msg = "krylov_tol must be >= 0"; return FDE_EINVAL; }
+  if (q->krylov_maxit <= 0) { *msg = "krylov_maxit must be > 0"; return FDE_EINVAL; }
+  if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
+  if (!(q->admm_tol >= 0) || !finite(q->admm_tol)) { *msg = "admm_tol must be >= 0"; return FDE_EINVAL; }
+  if (q->admm_maxit <= 0) { *msg = "admm_maxit must be > 0"; return FDE_EINVAL; }
+  return FDE_OK;
+}
+
+int validate(const fde_problem* p, const fde_admm_params* q, std::string* msg) {
+  if (!p) { *msg = "problem is NULL"; return FDE_EINVAL; }
+  const int dims[3] = {p->nx, p->ny, p->nt};
+  const char* names[3] = {"nx", "ny", "nt"};
+  for (int i = 0; i < 3; ++i) {
+    if (!length_supported(dims[i])) {
+      *msg = std::string(names[i]) + "=" + std::to_string(dims[i]) +
+             " unsupported: need 2^a*3^b (b <= 1) between 4 and 1024";
+      return FDE_EINVAL;
+    }
+  }
+  if (!(p->T > 0) || !finite(p->T)) { *msg = "T must be finite and > 0"; return FDE_EINVAL; }
+  if (!(p->alpha > 1.0 && p->alpha <= 2.0)) { *msg = fmt("alpha=%g outside (1, 2]", p->alpha); return FDE_EINVAL; }
+  if (!(p->beta > 1.0 && p->beta <= 2.0)) { *msg = fmt("beta=%g outside (1, 2]", p->beta); return FDE_EINVAL; }
+  if (p->ctrl_sign != 1.0 && p->ctrl_sign != -1.0) { *msg = "ctrl_sign must be +1 or -1"; return FDE_EINVAL; }
+  if (p->psi_scaling != 0 && p->psi_scaling != 1) { *msg = "psi_scaling must be 0 or 1"; return FDE_EINVAL; }
+  if (p->obj_weights != 0 && p->obj_weights != 1) { *msg = "obj_weights must be 0 or 1"; return FDE_EINVAL; }
+  if (p->precond_fp32 != 0 && p->precond_fp32 != 1) { *msg = "precond_fp32 must be 0 or 1"; return FDE_EINVAL; }
+  const size_t plane = (size_t)p->nx * p->ny;
+  const double* fields[2] = {p->dplus, p->dminus};
+  for (int f = 0; f < 2; ++f) {
+    if (!fields[f]) continue;
+    for (size_t i = 0; i < plane; ++i) {
+      if (!(fields[f][i] >= 0) || !finite(fields[f][i])) {
+        *msg = "coefficient fields must be finite and >= 0";
+        return FDE_EINVAL;
+      }
+    }
+  }
+  return validate_params(q, msg);
+}
+
+std::vector<double> grunwald_weights(double a, int n) {
+  // g_0 = 1, g_k = (1 - (a+1)/k) g_{k-1} (Sec. 4, recurrence under eq. (4.4))
+  std::vector<double> g(n + 1);
+  g[0] = 1.0;
+  for (int k = 1; k <= n; ++k) g[k] = (1.0 - (a + 1.0) / k) * g[k - 1];
+  return g;
+}
+
+std::vector<double> grunwald_weight_derivs(double a, int n) {
+  // differentiate the recurrence in a: g'_0 = 0, g'_k = (1-(a+1)/k) g'_{k-1} - g_{k-1}/k
+  std::vector<double> g = grunwald_weights(a, n);
+  std::vector<double> d(n + 1);
+  d[0] = 0.0;
+  for (int k = 1; k <= n; ++k) d[k] = (1.0 - (a + 1.0) / k) * d[k - 1] - g[k - 1] / k;
+  return d;
+}
+
+std::vector<cd> twiddles(int L) {
+  std::vector<cd> w(L);
+  for (int m = 0; m < L; ++m) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+    w[m] = cd((double)std::cos(ang), (double)std::sin(ang));
+  }
+  return w;
+}
+
+std::vector<cd> dft(const std::vector<cd>& c) {
+  // direct O(L^2) sum with the phase index reduced mod L, long double accumulation
+  const int L = (int)c.size();
+  std::vector<long double> cr(L), si(L);
+  for (int m = 0; m < L; ++m) {
+    const long double ang = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+    cr[m] = std::cos(ang);
+    si[m] = std::sin(ang);
+  }
+  std::vector<cd> out(L);
+  for (int k = 0; k < L; ++k) {
+    long double re = 0, im = 0;
+    for (int m = 0; m < L; ++m) {
+      const int idx = (int)(((long long)k * m) % L);
+      // exp(-i ang) = cos - i sin
+      const long double a = c[m].real(), b = c[m].imag();
+      re += a * cr[idx] + b * si[idx];
+      im += b * cr[idx] - a * si[idx];
+    }
+    out[k] = cd((double)re, (double)im);
+  }
+  return out;
+}
+
+std::vector<cd> tchan_eigs(const std::vector<double>& t_pos, const std::vector<double>& t_neg) {
+  // T. Chan optimal circulant (closed form under eq. (5.1)):
+  //   c_i = ((n - i) t_i + i t_{i-n}) / n, eigenvalues = DFT(c) (Thm 2.2)
+  // t_pos[k] = t_k (k = 0..n-1), t_neg[k] = t_{-k} (k = 1..n-1; t_neg[0] unused)
+  const int n = (int)t_pos.size();
+  std::vector<cd> c(n);
+  for (int i = 0; i < n; ++i) {
+    const double ti = t_pos[i];
+    const double tin = (i > 0) ? t_neg[n - i] : 0.0;
+    c[i] = cd(((n - i) * ti + i * tin) / n, 0.0);
+  }
+  return dft(c);
+}
+
+namespace {
+
+// Toeplitz entries of the mean-coefficient operator c (dp G + dm G^T):
+// G[i][j] = g_{i-j+1}: t_k = g_{k+1} for k >= -1; G^T: t_k = g_{1-k} for k <= 1
+void mean_operator_entries(const std::vector<double>& g, double c, double dp, double dm, int n,
+                           std::vector<double>* tp, std::vector<double>* tn) {
+  tp->assign(n, 0.0);
+  tn->assign(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double v = dp * g[k + 1];
+    if (k <= 1) v += dm * g[1 - k];
+    (*tp)[k] = c * v;
+  }
+  for (int k = 1; k < n; ++k) {
+    double v = dm * g[k + 1];
+    if (k == 1) v += dp * g[0];
+    (*tn)[k] = c * v;
+  }
+}
+
+void build_axis(int n, double h, double order, double dp, double dm, bool var, AxisTables* ax) {
+  ax->n = n;
+  ax->h = h;
+  ax->order = order;
+  ax->c = -1.0 / (2.0 * std::cos(order * kPi / 2.0)) / std::pow(h, order);  // eq. (4.7)
+  ax->g = grunwald_weights(order, n);
+  ax->dg = grunwald_weight_derivs(order, n);
+  const int L = 2 * n;
+  // first column of the 2n circulant embedding G: (g_1, .., g_n, 0, .., 0, g_0)
+  auto embed = [&](const std::vector<double>& gg) {
+    std::vector<cd> col(L, cd(0, 0));
+    for (int k = 0; k < n; ++k) col[k] = gg[k + 1];
+    col[L - 1] = gg[0];
+    return dft(col);
+  };
+  const double s = ax->c / L;
+  std::vector<cd> lg = embed(ax->g);
+  std::vector<cd> ldg = embed(ax->dg);
+  ax->lamG.resize(L);
+  ax->lamGT.resize(L);
+  ax->lamFwd.resize(L);
+  ax->lamTr.resize(L);
+  ax->dopA.resize(L);
+  ax->dopB.resize(L);
+  // dL/da = kappa L + (c_a/h^a)(d+ G' + d- G'^T), kappa = (pi/2) tan(a pi/2) - ln h
+  const double kappa = (kPi / 2.0) * std::tan(order * kPi / 2.0) - std::log(h);
+  for (int k = 0; k < L; ++k) {
+    // G^T embeds as the reversed column: its eigenvalues are the conjugates
+    ax->lamG[k] = s * lg[k];
+    ax->lamGT[k] = s * std::conj(lg[k]);
+    ax->lamFwd[k] = s * (dp * lg[k] + dm * std::conj(lg[k]));
+    ax->lamTr[k] = s * (dp * std::conj(lg[k]) + dm * lg[k]);
+    if (var) {
+      ax->dopA[k] = s * (kappa * lg[k] + ldg[k]);
+      ax->dopB[k] = s * (kappa * std::conj(lg[k]) + std::conj(ldg[k]));
+    } else {
+      ax->dopA[k] = s * (kappa * (dp * lg[k] + dm * std::conj(lg[k])) + dp * ldg[k] + dm * std::conj(ldg[k]));
+      ax->dopB[k] = cd(0, 0);
+    }
+  }
+  std::vector<double> tp, tn;
+  mean_operator_entries(ax->g, ax->c, dp, dm, n, &tp, &tn);
+  ax->tchan = tchan_eigs(tp, tn);
+  ax->tw_emb = twiddles(L);
+  ax->tw = twiddles(n);
+}
+
+}  // namespace
+
+void set_admm_scalings(const fde_admm_params* q, Setup* s) {
+  const int nt = s->nt;
+  s->wts.assign(nt, 1.0);
+  if (s->obj_weights == 1) s->wts[nt - 1] = 0.5;  // trapezoidal, eq. (4.10)
+  s->My.resize(nt);
+  s->Mu.resize(nt);
+  s->Mp.resize(nt);
+  s->invMp.resize(nt);
+  for (int k = 0; k < nt; ++k) {
+    s->My[k] = q->rho * (s->wts[k] + s->e_y * s->e_y / q->delta);
+    s->Mu[k] = q->rho * (q->gamma * s->wts[k] + s->e_u * s->e_u / q->delta);
+    s->Mp[k] = s->k_u * s->k_u / s->Mu[k] + q->delta / q->rho;
+    s->invMp[k] = 1.0 / s->Mp[k];
+  }
+  // preconditioner: J1 approximated by jbar = 1 (eq. (3.10) with circulant blocks)
+  const double jbar = 1.0;
+  s->a = q->rho * (jbar + s->e_y * s->e_y / q->delta);
+  const double mbar = s->k_u * s->k_u / (q->rho * (q->gamma * jbar + s->e_u * s->e_u / q->delta)) + q->delta / q->rho;
+  s->inv_mbar = 1.0 / mbar;
+}
+
+int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::string* msg) {
+  const int st = validate(p, q, msg);
+  if (st != FDE_OK) return st;
+  s->nx = p->nx;
+  s->ny = p->ny;
+  s->nt = p->nt;
+  s->T = p->T;
+  s->ht = p->T / p->nt;
+  const double hx = 1.0 / (p->nx + 1), hy = 1.0 / (p->ny + 1);
+  s->var = (p->dplus != nullptr) || (p->dminus != nullptr);
+  const size_t plane = (size_t)p->nx * p->ny;
+  s->dplus.assign(p->dplus ? p->dplus : (const double*)nullptr, p->dplus ? p->dplus + plane : nullptr);
+  s->dminus.assign(p->dminus ? p->dminus : (const double*)nullptr, p->dminus ? p->dminus + plane : nullptr);
+  if (s->var) {
+    if (s->dplus.empty()) s->dplus.assign(plane, 1.0);
+    if (s->dminus.empty()) s->dminus.assign(plane, 1.0);
+  }
+  // arithmetic means over the interior nodes enter the circulant preconditioner
+  auto mean = [&](const std::vector<double>& f) {
+    if (f.empty()) return 1.0;
+    long double acc = 0;
+    for (double v : f) acc += v;
+    return (double)(acc / f.size());
+  };
+  s->dbar_plus = mean(s->dplus);
+  s->dbar_minus = mean(s->dminus);
+  build_axis(p->nx, hx, p->alpha, s->dbar_plus, s->dbar_minus, s->var, &s->x);
+  build_axis(p->ny, hy, p->beta, s->dbar_plus, s->dbar_minus, s->var, &s->y);
+  // time: implicit Euler (I - Z)/ht; T. Chan column (1, -(nt-1)/nt, 0, ..)/ht
+  std::vector<double> tp(p->nt, 0.0), tn(p->nt, 0.0);
+  tp[0] = 1.0 / s->ht;
+  if (p->nt > 1) tp[1] = -1.0 / s->ht;
+  s->tchan_t = tchan_eigs(tp, tn);
+  s->tw_t = twiddles(p->nt);
+  // psi = min{ht, hx^alpha, hy^beta} (Sec. 5 with time order 1)
+  s->psi = p->psi_scaling ? std::fmin(s->ht, std::fmin(std::pow(hx, p->alpha), std::pow(hy, p->beta))) : 1.0;
+  s->e_y = 1.0;
+  s->e_u = p->psi_scaling ? s->psi : 1.0;
+  s->k_u = s->psi * p->ctrl_sign;
+  s->obj_weights = p->obj_weights;
+  set_admm_scalings(q, s);
+  return FDE_OK;
+}
+
+}  // namespace host
+}  // namespace fde

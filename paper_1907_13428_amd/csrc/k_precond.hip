@@ -1,0 +1,336 @@
+// The Schur-complement preconditioner z = S~^{-1} r of eq. (3.10), with the
+// 3-level T. Chan circulant C_3(B) of eq. (5.2): S~ = a I + C_3^* C_3 / mbar_p
+// is diagonalised by the 3-D DFT, with eigenvalues
+//     s(kx, ky, kt) = a + |psi (lam_t[kt] - lam_y[ky] - lam_x[kx])|^2 / mbar_p
+// computed in registers from the three 1-D tables (no N-sized eigen array).
+//
+// Passes (each one HBM sweep of the half spectrum [nt][ny][H], H = nx/2 + 1):
+//   1. x: real -> half spectrum, two real lines packed per complex FFT of
+//      length nx and separated with X1 = (Z + conj Z~)/2, X2 = (Z - conj Z~)/2i
+//      (fused with the PCG update r -= alpha q, x += alpha p and (r, r))
+//   2. y: complex FFT along y on column tiles staged through LDS
+//   3. t: complex FFT along t, divide by s * nx*ny*nt, inverse FFT along t
+//   4. y: inverse complex FFT
+//   5. x: half spectrum -> two real lines (Hermitian completion), fused (r, z)
+// TS is the spectrum precision: double, or float for the mixed form.
+#include "fde_fft.hpp"
+#include "fde_internal.hpp"
+#include "fde_reduce.hpp"
+
+namespace fde {
+
+constexpr int kPreThreads = 256;
+
+template <typename TS> struct PreTypes {
+  using V = cplx<TS>;
+};
+
+// ---------------------------------------------------------------------------
+// pass 1: x-direction real-to-complex
+// ---------------------------------------------------------------------------
+template <int L, typename TS, bool FUSE>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
+  using V = cplx<TS>;
+  constexpr int E = default_E(L);
+  constexpr int T = L / E;
+  constexpr int LPB = kPreThreads / T;
+  constexpr int H = L / 2 + 1;
+  __shared__ V lds[LPB * lpad_size(L)];
+  if (a.done && *a.done) return;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int nlines = a.ny * a.nt;
+  const int pair = blockIdx.x * LPB + g;
+  const int l0 = 2 * pair, l1 = 2 * pair + 1;
+  const bool h0 = l0 < nlines, h1 = l1 < nlines;
+  LineLds<V> buf{lds + g * lpad_size(L), 1};
+  const V* tw = reinterpret_cast<const V*>(a.twx);
+  double alpha = 0.0;
+  if constexpr (FUSE) alpha = a.scal[kAlpha];
+
+  V v[E];
+  double rr = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    double r0 = 0.0, r1 = 0.0;
+    if (h0) {
+      const size_t gi = (size_t)l0 * L + i;
+      r0 = a.r[gi];
+      if constexpr (FUSE) {
+        r0 -= alpha * a.q[gi];
+        a.r[gi] = r0;
+        a.xvec[gi] += alpha * a.pvec[gi];
+      }
+    }
+    if (h1) {
+      const size_t gi = (size_t)l1 * L + i;
+      r1 = a.r[gi];
+      if constexpr (FUSE) {
+        r1 -= alpha * a.q[gi];
+        a.r[gi] = r1;
+        a.xvec[gi] += alpha * a.pvec[gi];
+      }
+    }
+    rr += r0 * r0 + r1 * r1;
+    v[e] = V{TS(r0), TS(r1)};
+  }
+  if constexpr (FUSE) {
+    const double s = block_sum<kPreThreads>(rr);
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+  }
+
+  line_fft<L, E, -1>(v, buf, t, tw);
+
+  // Hermitian separation needs Z[(L - i) mod L] from another thread
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) buf[t + T * e] = v[e];
+  __syncthreads();
+  V* spec = reinterpret_cast<V*>(a.spec);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    if (i >= H) continue;
+    const V z = v[e];
+    const V zc = buf[(L - i) % L];
+    const V x1 = V{TS(0.5) * (z.x + zc.x), TS(0.5) * (z.y - zc.y)};
+    const V x2 = V{TS(0.5) * (z.y + zc.y), TS(-0.5) * (z.x - zc.x)};
+    if (h0) spec[(size_t)l0 * H + i] = x1;
+    if (h1) spec[(size_t)l1 * H + i] = x2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// passes 2/4 (y) and 3 (t): complex lines across rows of a [rows][H] plane,
+// P columns per block staged through LDS
+// ---------------------------------------------------------------------------
+template <int L> struct CCfg {
+  static constexpr int E = default_E(L);
+  static constexpr int T = L / E;
+  static constexpr int P = (kPreThreads / T) > 16 ? 16 : (kPreThreads / T);
+  static constexpr int NT = ((P * T + 63) / 64) * 64;
+  static constexpr int RS = P + 1;
+};
+
+// MODE 0: y-direction, sign SIGN.  MODE 1: t-direction with the eigenvalue division.
+template <int L, typename TS, int MODE, int SIGN>
+__global__ __launch_bounds__(CCfg<L>::NT) void k_pre_cc(PrecondArgs a) {
+  using V = cplx<TS>;
+  using C = CCfg<L>;
+  constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
+  __shared__ V lds[lpad_size(L) * RS];
+  if (a.done && *a.done) return;
+  const int H = a.H;
+  const int tiles = (H + P - 1) / P;
+  const int outer = blockIdx.x / tiles;  // MODE 0: time slice; MODE 1: ky row
+  const int k0 = (blockIdx.x % tiles) * P;
+  // element (line index i, column c) address in the spectrum
+  size_t base, stride;
+  if (MODE == 0) {
+    base = (size_t)outer * a.ny * H;
+    stride = H;
+  } else {
+    base = (size_t)outer * H;
+    stride = (size_t)a.ny * H;
+  }
+  V* spec = reinterpret_cast<V*>(a.spec);
+  const V* tw = reinterpret_cast<const V*>(MODE == 0 ? a.twy : a.twt);
+  const int tid = threadIdx.x;
+  const bool active = tid < P * T;
+  const int g = active ? tid / T : P, t = tid % T;
+  LineLds<V> buf{lds + g, RS};
+
+  for (int idx = tid; idx < L * P; idx += NT) {
+    const int row = idx / P, c = idx % P;
+    V val = V{TS(0), TS(0)};
+    if (k0 + c < H) val = spec[base + row * stride + k0 + c];
+    lds[lpad(row) * RS + c] = val;
+  }
+  __syncthreads();
+  V v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = buf[t + T * e];
+  __syncthreads();
+
+  if constexpr (MODE == 0) {
+    line_fft<L, E, SIGN>(v, buf, t, tw);
+  } else {
+    line_fft<L, E, -1>(v, buf, t, tw);
+    const int kx = k0 + g;
+    const int ky = outer;
+    const double2 lx = a.lam_x[kx < H ? kx : 0];
+    const double2 ly = a.lam_y[ky];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kt = t + T * e;
+      const double2 lt = a.lam_t[kt];
+      const double re = a.psi * (lt.x - ly.x - lx.x);
+      const double im = a.psi * (lt.y - ly.y - lx.y);
+      const double s = a.a + (re * re + im * im) * a.inv_mbar;
+      const TS f = TS(a.inv_n / s);
+      v[e] = V{v[e].x * f, v[e].y * f};
+    }
+    line_fft<L, E, +1>(v, buf, t, tw);
+  }
+
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) buf[t + T * e] = v[e];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < L * P; idx += NT) {
+    const int row = idx / P, c = idx % P;
+    if (k0 + c < H) spec[base + row * stride + k0 + c] = lds[lpad(row) * RS + c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 5: half spectrum -> real lines, fused partial sums of (r, z)
+// ---------------------------------------------------------------------------
+template <int L, typename TS, bool DOT>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
+  using V = cplx<TS>;
+  constexpr int E = default_E(L);
+  constexpr int T = L / E;
+  constexpr int LPB = kPreThreads / T;
+  constexpr int H = L / 2 + 1;
+  __shared__ V lds[LPB * lpad_size(L)];
+  if (a.done && *a.done) return;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int nlines = a.ny * a.nt;
+  const int pair = blockIdx.x * LPB + g;
+  const int l0 = 2 * pair, l1 = 2 * pair + 1;
+  const bool h0 = l0 < nlines, h1 = l1 < nlines;
+  LineLds<V> buf{lds + g * lpad_size(L), 1};
+  const V* tw = reinterpret_cast<const V*>(a.twx);
+  const V* spec = reinterpret_cast<const V*>(a.spec);
+
+  V v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    const bool lo = i < H;
+    const int k = lo ? i : L - i;
+    V x1 = V{TS(0), TS(0)}, x2 = V{TS(0), TS(0)};
+    if (h0) x1 = spec[(size_t)l0 * H + k];
+    if (h1) x2 = spec[(size_t)l1 * H + k];
+    if (!lo) {
+      x1.y = -x1.y;
+      x2.y = -x2.y;
+    }
+    v[e] = V{x1.x - x2.y, x1.y + x2.x};  // X1 + i X2
+  }
+  line_fft<L, E, +1>(v, buf, t, tw);
+  double rz = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    if (h0) {
+      const size_t gi = (size_t)l0 * L + i;
+      const double z0 = double(v[e].x);
+      a.z[gi] = z0;
+      if constexpr (DOT) rz += a.r[gi] * z0;
+    }
+    if (h1) {
+      const size_t gi = (size_t)l1 * L + i;
+      const double z1 = double(v[e].y);
+      a.z[gi] = z1;
+      if constexpr (DOT) rz += a.r[gi] * z1;
+    }
+  }
+  if constexpr (DOT) {
+    const double s = block_sum<kPreThreads>(rz);
+    if (threadIdx.x == 0) a.partial2[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+#define FDE_FOR_DIM_LENGTHS(X) \
+  X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+template <int L, typename TS>
+static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) {
+  constexpr int LPB = kPreThreads / (L / default_E(L));
+  const int pairs = (a.ny * a.nt + 1) / 2;
+  const int blocks = (pairs + LPB - 1) / LPB;
+  if (nb) *nb = blocks;
+  if (fwd) {
+    if (a.q) k_pre_xfwd<L, TS, true><<<blocks, kPreThreads, 0, s>>>(a);
+    else k_pre_xfwd<L, TS, false><<<blocks, kPreThreads, 0, s>>>(a);
+  } else {
+    if (a.partial2) k_pre_xinv<L, TS, true><<<blocks, kPreThreads, 0, s>>>(a);
+    else k_pre_xinv<L, TS, false><<<blocks, kPreThreads, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <int L, typename TS>
+static hipError_t pre_y(const PrecondArgs& a, int sign, hipStream_t s) {
+  using C = CCfg<L>;
+  const int blocks = ((a.H + C::P - 1) / C::P) * a.nt;
+  if (sign < 0) k_pre_cc<L, TS, 0, -1><<<blocks, C::NT, 0, s>>>(a);
+  else k_pre_cc<L, TS, 0, +1><<<blocks, C::NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int L, typename TS>
+static hipError_t pre_t(const PrecondArgs& a, hipStream_t s) {
+  using C = CCfg<L>;
+  const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
+  k_pre_cc<L, TS, 1, -1><<<blocks, C::NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename TS>
+static hipError_t precond_T(const PrecondArgs& a, int stage, hipStream_t s, int* nb_fwd, int* nb_inv) {
+  hipError_t err = hipSuccess;
+  // pass 1 (x forward); partial sums of r.r only when fused
+  if (stage != 2) {
+    switch (a.nx) {
+#define CASE(Lv) case Lv: err = pre_x<Lv, TS>(a, true, s, nb_fwd); break;
+      FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+      default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess || stage == 1) return err;
+  }
+  const PrecondArgs& a2 = a;
+  switch (a.ny) {
+#define CASE(Lv) case Lv: err = pre_y<Lv, TS>(a2, -1, s); break;
+    FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess) return err;
+  switch (a.nt) {
+#define CASE(Lv) case Lv: err = pre_t<Lv, TS>(a2, s); break;
+    FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess) return err;
+  switch (a.ny) {
+#define CASE(Lv) case Lv: err = pre_y<Lv, TS>(a2, +1, s); break;
+    FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  if (err != hipSuccess) return err;
+  switch (a.nx) {
+#define CASE(Lv) case Lv: err = pre_x<Lv, TS>(a, false, s, nb_inv); break;
+    FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return err;
+}
+
+hipError_t launch_precond_stage(const PrecondArgs& a, bool fp32, int stage, hipStream_t s, int* nb_fwd,
+                                int* nb_inv) {
+  return fp32 ? precond_T<float>(a, stage, s, nb_fwd, nb_inv) : precond_T<double>(a, stage, s, nb_fwd, nb_inv);
+}
+
+}  // namespace fde

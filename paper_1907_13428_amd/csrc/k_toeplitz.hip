@@ -1,0 +1,312 @@
+// Toeplitz line passes of the constraint operator D = C_t (x) I - I (x)(L_x (+) L_y)
+// (eq. (4.9)) and its transpose, by circulant embedding and FFT (Table 1, Sec. 5).
+//
+// A length-n Toeplitz product T v is the first n entries of C [v; 0], C the
+// 2n circulant whose first column is (t_0 .. t_{n-1}, 0, t_{-(n-1)} .. t_{-1});
+// C = F^{-1} diag(lambda) F.  Two real lines are packed into one complex
+// line (the operators are real), so one forward and one inverse complex FFT
+// of length 2n serve two lines.  The host tables lambda already carry the
+// factor c_a / h^a of eq. (4.7) and 1/(2n).
+//
+// Variable coefficients (row scaling d+ G + d- G^T, or G^T d+ + G d- for the
+// transpose) need the G and G^T products separately: one forward and two
+// inverse transforms (forward operator) or two forward and one inverse
+// (transpose).
+#include "fde_fft.hpp"
+#include "fde_internal.hpp"
+#include "fde_reduce.hpp"
+
+namespace fde {
+
+constexpr int kLineThreads = 256;
+
+// ---------------------------------------------------------------------------
+// x-pass: contiguous lines (t, j), with the time difference fused
+// ---------------------------------------------------------------------------
+template <int L, bool VAR, bool TRANS>
+__global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
+  constexpr int E = default_E(L);
+  constexpr int T = L / E;
+  static_assert(T <= kLineThreads, "line too long for one block");
+  constexpr int LPB = kLineThreads / T;  // packed line pairs per block
+  constexpr int n = L / 2;
+  __shared__ double2 lds[LPB * lpad_size(L)];
+  if (a.done && *a.done) return;
+
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int nlines = a.ny * a.nt;
+  const int pair = blockIdx.x * LPB + g;
+  const int l0 = 2 * pair, l1 = 2 * pair + 1;
+  const bool h0 = l0 < nlines, h1 = l1 < nlines;
+  LineLds<double2> buf{lds + g * lpad_size(L), 1};
+  const double* __restrict__ in = a.in;
+
+  double2 v[E];
+  double2 w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    double x0 = 0.0, x1 = 0.0;
+    if (i < n) {
+      if (h0) x0 = in[(size_t)l0 * n + i];
+      if (h1) x1 = in[(size_t)l1 * n + i];
+    }
+    if constexpr (VAR && TRANS) {
+      double p0 = 0, p1 = 0, m0 = 0, m1 = 0;
+      if (i < n) {
+        if (h0) { p0 = a.dplus[(l0 % a.ny) * n + i]; m0 = a.dminus[(l0 % a.ny) * n + i]; }
+        if (h1) { p1 = a.dplus[(l1 % a.ny) * n + i]; m1 = a.dminus[(l1 % a.ny) * n + i]; }
+      }
+      v[e] = double2{p0 * x0, p1 * x1};
+      w[e] = double2{m0 * x0, m1 * x1};
+    } else {
+      v[e] = double2{x0, x1};
+    }
+  }
+
+  line_fft<L, E, -1>(v, buf, t, a.tw);
+  if constexpr (VAR && TRANS) line_fft<L, E, -1>(w, buf, t, a.tw);
+
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    const double2 la = a.lamA[i];
+    if constexpr (VAR && TRANS) {
+      // transpose: G^T (d+ v) + G (d- v); host passes lamA = G^T, lamB = G
+      v[e] = cadd(cmul(v[e], la), cmul(w[e], a.lamB[i]));
+    } else if constexpr (VAR) {
+      w[e] = cmul(v[e], a.lamB[i]);  // G^T v
+      v[e] = cmul(v[e], la);         // G v
+    } else {
+      v[e] = cmul(v[e], la);
+    }
+  }
+
+  line_fft<L, E, +1>(v, buf, t, a.tw);
+  if constexpr (VAR && !TRANS) line_fft<L, E, +1>(w, buf, t, a.tw);
+
+  // epilogue: out = s_time * time difference + s_sp * spatial
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    if (i >= n) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int l = h ? l1 : l0;
+      if (!(h ? h1 : h0)) continue;
+      double sp = h ? v[e].y : v[e].x;
+      if constexpr (VAR && !TRANS) {
+        const int j = l % a.ny;
+        sp = a.dplus[j * n + i] * sp + a.dminus[j * n + i] * (h ? w[e].y : w[e].x);
+      }
+      const size_t gi = (size_t)l * n + i;
+      double val = a.s_sp * sp;
+      if (a.s_time != 0.0) {
+        const int tt = l / a.ny;
+        double nb = 0.0;
+        if constexpr (TRANS) {
+          if (tt + 1 < a.nt) nb = in[gi + (size_t)a.ny * n];
+        } else {
+          if (tt > 0) nb = in[gi - (size_t)a.ny * n];
+        }
+        val += a.s_time * (in[gi] - nb);
+      }
+      a.out[gi] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y-pass: a block owns one time slice and 2P adjacent x-columns; the tile is
+// staged through LDS so that every global access is row-contiguous
+// ---------------------------------------------------------------------------
+template <int L> struct YCfg {
+  static constexpr int E = default_E(L);
+  static constexpr int T = L / E;
+  static constexpr int P = (kLineThreads / T) > 8 ? 8 : (kLineThreads / T);  // column pairs per block
+  static constexpr int NT = ((P * T + 63) / 64) * 64;                       // threads per block
+  static constexpr int RS = P + 1;                                          // LDS row stride
+};
+
+template <int L, bool VAR, bool TRANS>
+__global__ __launch_bounds__(YCfg<L>::NT) void k_ypass(LinePassArgs a) {
+  using C = YCfg<L>;
+  constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
+  constexpr int n = L / 2;
+  constexpr int TX = 2 * P;
+  __shared__ double2 lds[lpad_size(L) * RS];
+  if (a.done && *a.done) return;
+
+  const int nx = a.nx;
+  const int tiles = (nx + TX - 1) / TX;
+  const int slice = blockIdx.x / tiles;
+  const int x0 = (blockIdx.x % tiles) * TX;
+  const size_t sbase = (size_t)slice * n * nx;
+  double* ldsd = reinterpret_cast<double*>(lds);
+  const int tid = threadIdx.x;
+  // threads beyond P*T (block rounded up to whole wavefronts) run the FFT on
+  // the spare LDS column P, which holds no data, and store nothing
+  const bool active = tid < P * T;
+  const int g = active ? tid / T : P, t = tid % T;
+  LineLds<double2> buf{lds + g, RS};
+
+  // cooperative tile load (rows 0..n-1; transposed-variable case also d- v in rows n..2n-1)
+  for (int idx = tid; idx < n * TX; idx += NT) {
+    const int row = idx / TX, c = idx % TX, x = x0 + c;
+    double val = 0.0;
+    double val2 = 0.0;
+    if (x < nx) {
+      const double vin = a.in[sbase + (size_t)row * nx + x];
+      if constexpr (VAR && TRANS) {
+        val = a.dplus[row * nx + x] * vin;
+        val2 = a.dminus[row * nx + x] * vin;
+      } else {
+        val = vin;
+      }
+    }
+    ldsd[2 * (lpad(row) * RS + (c >> 1)) + (c & 1)] = val;
+    if constexpr (VAR && TRANS) ldsd[2 * (lpad(row + n) * RS + (c >> 1)) + (c & 1)] = val2;
+  }
+  __syncthreads();
+
+  double2 v[E];
+  double2 w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    v[e] = (i < n) ? buf[i] : double2{0.0, 0.0};
+    if constexpr (VAR && TRANS) w[e] = (i < n) ? buf[i + n] : double2{0.0, 0.0};
+  }
+  __syncthreads();
+
+  line_fft<L, E, -1>(v, buf, t, a.tw);
+  if constexpr (VAR && TRANS) line_fft<L, E, -1>(w, buf, t, a.tw);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = t + T * e;
+    const double2 la = a.lamA[i];
+    if constexpr (VAR && TRANS) {
+      v[e] = cadd(cmul(v[e], la), cmul(w[e], a.lamB[i]));
+    } else if constexpr (VAR) {
+      w[e] = cmul(v[e], a.lamB[i]);
+      v[e] = cmul(v[e], la);
+    } else {
+      v[e] = cmul(v[e], la);
+    }
+  }
+  line_fft<L, E, +1>(v, buf, t, a.tw);
+  if constexpr (VAR && !TRANS) line_fft<L, E, +1>(w, buf, t, a.tw);
+
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t + T * e;
+      if (i < n) {
+        buf[i] = v[e];
+        if constexpr (VAR && !TRANS) buf[i + n] = w[e];
+      }
+    }
+  }
+  __syncthreads();
+
+  const double osc = a.oscale ? a.oscale[slice] : 1.0;
+  const double esc = a.extra ? a.escale[slice] : 0.0;
+  double dot = 0.0;
+  for (int idx = tid; idx < n * TX; idx += NT) {
+    const int row = idx / TX, c = idx % TX, x = x0 + c;
+    if (x >= nx) continue;
+    double sp = ldsd[2 * (lpad(row) * RS + (c >> 1)) + (c & 1)];
+    if constexpr (VAR && !TRANS) {
+      const double sp2 = ldsd[2 * (lpad(row + n) * RS + (c >> 1)) + (c & 1)];
+      sp = a.dplus[row * nx + x] * sp + a.dminus[row * nx + x] * sp2;
+    }
+    const size_t gi = sbase + (size_t)row * nx + x;
+    double val = a.s_sp * sp;
+    if (a.acc) val += a.acc[gi];
+    val *= osc;
+    if (a.extra) val += esc * a.extra[gi];
+    a.out[gi] = val;
+    if (a.dotv) dot += a.dotv[gi] * val;
+  }
+  if (a.dotv) {
+    const double s = block_sum<NT>(dot);
+    if (tid == 0) a.partial[blockIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+#define FDE_FOR_EMBED_LENGTHS(X) \
+  X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+bool fft_length_supported(int L) {
+  switch (L) {
+#define CASE(Lv) case Lv:
+    FDE_FOR_EMBED_LENGTHS(CASE)
+#undef CASE
+    return true;
+    case 4:
+    case 6:
+      return true;
+    default:
+      return false;
+  }
+}
+
+template <int L>
+static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  constexpr int E = default_E(L);
+  constexpr int LPB = kLineThreads / (L / E);
+  const int nlines = a.ny * a.nt;
+  const int pairs = (nlines + 1) / 2;
+  const int blocks = (pairs + LPB - 1) / LPB;
+  if (nb) *nb = blocks;
+  if (var) {
+    if (tr) k_xpass<L, true, true><<<blocks, kLineThreads, 0, s>>>(a);
+    else k_xpass<L, true, false><<<blocks, kLineThreads, 0, s>>>(a);
+  } else {
+    if (tr) k_xpass<L, false, true><<<blocks, kLineThreads, 0, s>>>(a);
+    else k_xpass<L, false, false><<<blocks, kLineThreads, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t ypass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  using C = YCfg<L>;
+  const int tiles = (a.nx + 2 * C::P - 1) / (2 * C::P);
+  const int blocks = tiles * a.nt;
+  if (nb) *nb = blocks;
+  if (var) {
+    if (tr) k_ypass<L, true, true><<<blocks, C::NT, 0, s>>>(a);
+    else k_ypass<L, true, false><<<blocks, C::NT, 0, s>>>(a);
+  } else {
+    if (tr) k_ypass<L, false, true><<<blocks, C::NT, 0, s>>>(a);
+    else k_ypass<L, false, false><<<blocks, C::NT, 0, s>>>(a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_xpass(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  switch (2 * a.nx) {
+#define CASE(Lv) case Lv: return xpass_L<Lv>(a, tr, var, s, nb);
+    FDE_FOR_EMBED_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ypass(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  switch (2 * a.ny) {
+#define CASE(Lv) case Lv: return ypass_L<Lv>(a, tr, var, s, nb);
+    FDE_FOR_EMBED_LENGTHS(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fde

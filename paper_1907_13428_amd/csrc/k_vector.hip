@@ -1,0 +1,267 @@
+// Elementwise and reduction kernels of the Krylov loop and the ADMM iteration.
+//
+// Reductions are deterministic: every block writes one partial sum (fixed
+// intra-block order) and a single-block finalize kernel adds the partials in
+// index order.  No floating-point atomics are used, so repeated runs are
+// bitwise identical.
+#include "fde_internal.hpp"
+#include "fde_reduce.hpp"
+
+namespace fde {
+
+__device__ __forceinline__ bool is_done(const int* done) { return done && *done; }
+
+// Sum of partial[0..n) in fixed order; valid in thread 0 of the (single) block.
+__device__ __forceinline__ double ordered_sum(const double* partial, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) s += partial[i];
+  return block_sum<kBlock>(s);
+}
+
+// ---------------------------------------------------------------------------
+// PCG scalar steps (one block)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pcg_scalar(int op, const double* partial, int n, double* scal,
+                                                       int* ints, double tol2, int maxit) {
+  if (op != FIN_INIT && op != FIN_DOT && ints[kDone]) return;
+  const double s0 = ordered_sum(partial, n);
+  double s1 = 0.0;
+  if (op == FIN_INIT) s1 = ordered_sum(partial + n, n);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case FIN_INIT: {
+      scal[kTol2] = tol2;
+      ints[kMaxit] = maxit;
+      scal[kRR] = s0;
+      scal[kBB] = s1;
+      ints[kIter] = 0;
+      ints[kDone] = 0;
+      ints[kConv] = 0;
+      if (s0 != s0 || s1 != s1) {
+        ints[kDone] = 1;
+        ints[kConv] = -1;
+      } else if (s1 == 0.0 || s0 <= scal[kTol2] * s1) {  // b = 0: the solution is x = 0
+        ints[kDone] = 1;
+        ints[kConv] = 1;
+      }
+      break;
+    }
+    case FIN_RZ0:
+      scal[kRZ] = s0;
+      break;
+    case FIN_ALPHA:
+      scal[kPQ] = s0;
+      scal[kAlpha] = scal[kRZ] / s0;
+      break;
+    case FIN_CONV: {
+      scal[kRR] = s0;
+      const int it = ints[kIter] + 1;
+      ints[kIter] = it;
+      if (s0 != s0) {
+        ints[kDone] = 1;
+        ints[kConv] = -1;
+      } else if (s0 <= scal[kTol2] * scal[kBB]) {
+        ints[kDone] = 1;
+        ints[kConv] = 1;
+      } else if (it >= ints[kMaxit]) {
+        ints[kDone] = 1;
+        ints[kConv] = 0;
+      }
+      break;
+    }
+    case FIN_BETA: {
+      const double rz = scal[kRZ];
+      scal[kBeta] = s0 / rz;
+      scal[kRZ] = s0;
+      break;
+    }
+    case FIN_DOT:
+      scal[kDot] = s0;
+      break;
+  }
+}
+
+hipError_t launch_pcg_scalar(int op, const double* partial, int n, double* scal, int* ints, hipStream_t s,
+                             double tol2, int maxit) {
+  k_pcg_scalar<<<1, kBlock, 0, s>>>(op, partial, n, scal, ints, tol2, maxit);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// vector ops
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_vec(int op, int64_t n, const double* __restrict__ a,
+                                                const double* __restrict__ b, double* c,
+                                                const double* scal, double* partial, const int* done) {
+  if (is_done(done)) return;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double s0 = 0.0, s1 = 0.0;
+  switch (op) {
+    case VEC_RESID:
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const double av = a[i];
+        const double cv = av - b[i];
+        c[i] = cv;
+        s0 += cv * cv;
+        s1 += av * av;
+      }
+      break;
+    case VEC_PUPDATE: {
+      const double beta = scal[kBeta];
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = a[i] + beta * c[i];
+      return;
+    }
+    case VEC_COPY:
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = a[i];
+      return;
+    case VEC_DOT:
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) s0 += a[i] * b[i];
+      break;
+    case VEC_ZERO_IF_BB0:
+      if (scal[kBB] != 0.0) return;
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = 0.0;
+      return;
+    case VEC_SCALE: {
+      const double f = scal[kDot];
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = f * a[i];
+      return;
+    }
+    default:
+      return;
+  }
+  const double r0 = block_sum<kBlock>(s0);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r0;
+  if (op == VEC_RESID) {
+    const double r1 = block_sum<kBlock>(s1);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = r1;
+  }
+}
+
+static int vec_blocks(int64_t n) {
+  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, double* c,
+                           const double* scal, double* partial, const int* done, hipStream_t s,
+                           int* nblocks) {
+  const int blocks = vec_blocks(n);
+  if (nblocks) *nblocks = blocks;
+  k_vec<<<blocks, kBlock, 0, s>>>(op, n, a, b, c, scal, partial, done);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ADMM elementwise steps (Algorithm 1 with the merged x-step, scaled form)
+// ---------------------------------------------------------------------------
+// right-hand side pieces:
+//   Ru = rho(-e_u wu + e_u^2 zu/delta) + (1-rho) k_u p
+//   r  = k_u Ru / Mu - psi g + (delta/rho) p
+//   v  = (1-rho) p - r / Mp         (b = B^T v + c)
+//   c  = rho (J1 yhat - e_y wy + e_y^2 zy / delta)
+__global__ __launch_bounds__(kBlock) void k_admm_rhs(AdmmConsts k, AdmmFields f, double psi) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const double rho = k.rho, delta = k.delta;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < k.n; i += stride) {
+    const int t = (int)(i / k.plane);
+    const double p = f.p[i];
+    const double Ru = rho * (-k.e_u * f.wu[i] + k.e_u * k.e_u * f.zu[i] / delta) + (1.0 - rho) * k.k_u * p;
+    const double gv = f.g ? f.g[i] : 0.0;
+    const double r = k.k_u * Ru / k.Mu[t] - psi * gv + (delta / rho) * p;
+    f.Ru[i] = Ru;
+    f.r[i] = r;
+    f.v[i] = (1.0 - rho) * p - r / k.Mp[t];
+    f.c[i] = rho * (k.wts[t] * f.yhat[i] - k.e_y * f.wy[i] + k.e_y * k.e_y * f.zy[i] / delta);
+  }
+}
+
+hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s) {
+  k_admm_rhs<<<vec_blocks(k.n), kBlock, 0, s>>>(k, f, psi);
+  return hipGetLastError();
+}
+
+// recovery, projection, dual update and the three residual maxima:
+//   p = (By + r)/Mp ; u = (Ru - k_u p)/Mu
+//   zy = clip(y + delta wy/e_y) ; zu = clip(u + delta wu/e_u)
+//   wy += (rho/delta) e_y (y - zy) ; wu += (rho/delta) e_u (u - zu)
+//   max |By + k_u u - psi g|, max |y - zy|, max |u - zu|
+__global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields f, double psi) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const double rho = k.rho, delta = k.delta;
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < k.n; i += stride) {
+    const int t = (int)(i / k.plane);
+    const double By = f.By[i];
+    const double p = (By + f.r[i]) / k.Mp[t];
+    const double u = (f.Ru[i] - k.k_u * p) / k.Mu[t];
+    const double y = f.y[i];
+    const double wy = f.wy[i], wu = f.wu[i];
+    const double zy = fmin(fmax(y + delta * wy / k.e_y, k.ya), k.yb);
+    const double zu = fmin(fmax(u + delta * wu / k.e_u, k.ua), k.ub);
+    f.p[i] = p;
+    f.u[i] = u;
+    f.zy[i] = zy;
+    f.zu[i] = zu;
+    f.wy[i] = wy + (rho / delta) * k.e_y * (y - zy);
+    f.wu[i] = wu + (rho / delta) * k.e_u * (u - zu);
+    const double gv = f.g ? f.g[i] : 0.0;
+    m0 = nanmax(m0, fabs(By + k.k_u * u - psi * gv));
+    m1 = nanmax(m1, fabs(y - zy));
+    m2 = nanmax(m2, fabs(u - zu));
+  }
+  const double r0 = block_max<kBlock>(m0);
+  const double r1 = block_max<kBlock>(m1);
+  const double r2 = block_max<kBlock>(m2);
+  if (threadIdx.x == 0) {
+    f.partial[3 * blockIdx.x + 0] = r0;
+    f.partial[3 * blockIdx.x + 1] = r1;
+    f.partial[3 * blockIdx.x + 2] = r2;
+  }
+}
+
+hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
+                              int* nblocks) {
+  const int blocks = vec_blocks(k.n);
+  if (nblocks) *nblocks = blocks;
+  k_admm_update<<<blocks, kBlock, 0, s>>>(k, f, psi);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_max3(const double* partial, int nb, double* scal) {
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[c] = nanmax(m[c], partial[3 * i + c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double r = block_max<kBlock>(m[c]);
+    if (threadIdx.x == 0) scal[kResP + c] = r;
+  }
+}
+
+hipError_t launch_max3_finalize(const double* partial, int nb, double* scal, hipStream_t s) {
+  k_max3<<<1, kBlock, 0, s>>>(partial, nb, scal);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_fields(int64_t n, int plane, const double* wts,
+                                                        const double* y, const double* yhat, const double* p,
+                                                        double psi, double* dyhat, double* lam) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const int t = (int)(i / plane);
+    if (dyhat) dyhat[i] = -wts[t] * (y[i] - yhat[i]);
+    if (lam) lam[i] = psi * p[i];
+  }
+}
+
+hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
+                              const double* p, double psi, double* dyhat, double* lam, hipStream_t s) {
+  k_grad_fields<<<vec_blocks(n), kBlock, 0, s>>>(n, plane, wts, y, yhat, p, psi, dyhat, lam);
+  return hipGetLastError();
+}
+
+}  // namespace fde

@@ -1,0 +1,242 @@
+"""Thin Python binding of libfde.so (include/fde.h): argument marshalling only.
+
+Every step of the operator applies, the preconditioner, the Krylov solve and
+the ADMM iteration runs in the library's HIP kernels on the GPU; this module
+only converts arguments (torch CUDA tensors -> device pointers, the current
+HIP stream -> hipStream_t) and status codes -> exceptions.  The library must
+be built (``python -m paper_1907_13428_amd.build``); nothing here falls back
+to a CPU implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfde.so")
+
+FDE_OK, FDE_ENOTCONV = 0, 1
+FDE_EINVAL, FDE_ENOMEM, FDE_EHIP, FDE_ENONFINITE = -1, -2, -3, -4
+_STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -3: "FDE_EHIP",
+           -4: "FDE_ENONFINITE"}
+
+EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
+            "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_last_error",
+            "fde_version"]
+
+
+class FdeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nt", ctypes.c_int32), ("T", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("dplus", ctypes.POINTER(ctypes.c_double)), ("dminus", ctypes.POINTER(ctypes.c_double)),
+                ("ctrl_sign", ctypes.c_double), ("psi_scaling", ctypes.c_int32), ("obj_weights", ctypes.c_int32),
+                ("precond_fp32", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("delta", ctypes.c_double), ("rho", ctypes.c_double),
+                ("ya", ctypes.c_double), ("yb", ctypes.c_double), ("ua", ctypes.c_double), ("ub", ctypes.c_double),
+                ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
+                ("admm_tol", ctypes.c_double), ("admm_maxit", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("admm_iters", ctypes.c_int32), ("pcg_total", ctypes.c_int32), ("pcg_last", ctypes.c_int32),
+                ("pcg_max", ctypes.c_int32), ("r_p", ctypes.c_double), ("r_y", ctypes.c_double),
+                ("r_u", ctypes.c_double), ("t_total", ctypes.c_double), ("t_pcg", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfde.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with python -m paper_1907_13428_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        D = ctypes.POINTER(ctypes.c_double)
+        L.fde_validate.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params)]
+        L.fde_host_tables.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), D, D, D, D, D, D]
+        L.fde_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), P, ctypes.POINTER(P)]
+        L.fde_destroy.argtypes = [P]
+        L.fde_set_params.argtypes = [P, ctypes.POINTER(Params)]
+        L.fde_apply_A.argtypes = [P, P, P, ctypes.c_int]
+        L.fde_apply_S.argtypes = [P, P, P]
+        L.fde_precond.argtypes = [P, P, P]
+        L.fde_krylov.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
+        L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
+        L.fde_last_error.restype = ctypes.c_char_p
+        L.fde_version.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("fde_last_error", "fde_version"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, allow_notconv=True):
+    if status == FDE_OK or (allow_notconv and status == FDE_ENOTCONV):
+        return status
+    raise FdeError(status, lib().fde_last_error().decode())
+
+
+def make_problem(nx, ny, nt, alpha, beta, *, T=1.0, dplus=None, dminus=None, ctrl_sign=1.0, psi_scaling=1,
+                 obj_weights=0, precond_fp32=0):
+    """Build the C problem struct; the coefficient arrays are kept alive on it."""
+    import numpy as np
+
+    p = Problem(nx=nx, ny=ny, nt=nt, T=T, alpha=alpha, beta=beta, ctrl_sign=ctrl_sign,
+                psi_scaling=int(psi_scaling), obj_weights=int(obj_weights), precond_fp32=int(precond_fp32))
+    keep = []
+    for name, arr in (("dplus", dplus), ("dminus", dminus)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            if a.size != nx * ny:
+                raise ValueError(f"{name} must hold nx*ny values")
+            keep.append(a)
+            setattr(p, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    p._keep = keep
+    return p
+
+
+def make_params(gamma, *, delta=1.0, rho=1.0, ya=-math.inf, yb=math.inf, ua=-math.inf, ub=math.inf,
+                krylov_tol=1e-10, krylov_maxit=1000, tol_mode=0, admm_tol=1e-6, admm_maxit=100000):
+    return Params(gamma=gamma, delta=delta, rho=rho, ya=ya, yb=yb, ua=ua, ub=ub, krylov_tol=krylov_tol,
+                  krylov_maxit=krylov_maxit, tol_mode=tol_mode, admm_tol=admm_tol, admm_maxit=admm_maxit)
+
+
+def from_workload(w, precond_fp32=0, **overrides):
+    """(Problem, Params) from any object with the workload attributes."""
+    prob = make_problem(w.nx, w.ny, w.nt, w.alpha, w.beta, T=w.T, dplus=w.dplus, dminus=w.dminus,
+                        ctrl_sign=w.ctrl_sign, psi_scaling=w.psi_scaling, obj_weights=w.obj_weights,
+                        precond_fp32=precond_fp32)
+    kw = dict(delta=w.delta, rho=w.rho, ya=w.ya, yb=w.yb, ua=w.ua, ub=w.ub, krylov_tol=w.krylov_tol,
+              krylov_maxit=w.krylov_maxit, admm_tol=w.admm_tol, admm_maxit=w.admm_maxit)
+    kw.update(overrides)
+    return prob, make_params(w.gamma, **kw)
+
+
+def validate(prob, prm):
+    return _check(lib().fde_validate(ctypes.byref(prob), ctypes.byref(prm)), allow_notconv=False)
+
+
+def host_tables(prob, prm):
+    """Host-only setup tables (no GPU use): scalars, T. Chan eigenvalues, weights."""
+    import numpy as np
+
+    scal = np.zeros(8)
+    lx = np.zeros(2 * prob.nx)
+    ly = np.zeros(2 * prob.ny)
+    lt = np.zeros(2 * prob.nt)
+    gx = np.zeros(prob.nx + 1)
+    gy = np.zeros(prob.ny + 1)
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().fde_host_tables(ctypes.byref(prob), ctypes.byref(prm), ptr(scal), ptr(lx), ptr(ly), ptr(lt),
+                                 ptr(gx), ptr(gy)), allow_notconv=False)
+    c = lambda a: a[0::2] + 1j * a[1::2]
+    keys = ["psi", "hx", "hy", "ht", "a", "inv_mbar", "e_u", "k_u"]
+    return dict(zip(keys, scal.tolist()), lam_x=c(lx), lam_y=c(ly), lam_t=c(lt), gx=gx, gy=gy)
+
+
+def _dptr(t, name="tensor"):
+    if t is None:
+        return None
+    import torch
+
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns an fde_ctx (device tables + workspace) bound to a HIP stream."""
+
+    def __init__(self, prob: Problem, prm: Params, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required (libfde.so runs on gfx950)")
+        self.prob, self.prm = prob, prm
+        self.shape = (prob.nt, prob.ny, prob.nx)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        _check(lib().fde_create(ctypes.byref(prob), ctypes.byref(prm), ctypes.c_void_p(s.cuda_stream),
+                                ctypes.byref(h)), allow_notconv=False)
+        self._h = h
+
+    # -- lifecycle -------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().fde_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_params(self, prm: Params):
+        _check(lib().fde_set_params(self._h, ctypes.byref(prm)), allow_notconv=False)
+        self.prm = prm
+
+    # -- entry points ----------------------------------------------------
+    def apply_A(self, x, y, transpose=False):
+        _check(lib().fde_apply_A(self._h, _dptr(x, "x"), _dptr(y, "y"), int(transpose)), False)
+        return y
+
+    def apply_S(self, x, y):
+        _check(lib().fde_apply_S(self._h, _dptr(x, "x"), _dptr(y, "y")), False)
+        return y
+
+    def precond(self, r, z):
+        _check(lib().fde_precond(self._h, _dptr(r, "r"), _dptr(z, "z")), False)
+        return z
+
+    def krylov(self, b, x):
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        st = _check(lib().fde_krylov(self._h, _dptr(b, "b"), _dptr(x, "x"), ctypes.byref(it), ctypes.byref(rel)))
+        return it.value, rel.value, st
+
+    def admm_solve(self, yhat, g=None, state=None):
+        """Run ADMM; `state` = dict of y, u, zy, zu, p, wy, wu tensors (zeros if None),
+        updated in place.  Returns (state, stats dict, status)."""
+        import torch
+
+        if state is None:
+            state = {k: torch.zeros(self.shape, dtype=torch.float64, device=yhat.device)
+                     for k in ("y", "u", "zy", "zu", "p", "wy", "wu")}
+        st = Stats()
+        args = [_dptr(state[k], k) for k in ("y", "u", "zy", "zu", "p", "wy", "wu")]
+        status = _check(lib().fde_admm_solve(self._h, _dptr(yhat, "yhat"), _dptr(g, "g"), *args,
+                                             ctypes.byref(st)))
+        return state, st.as_dict(), status
+
+    def grad(self, yhat, y, p, wy=None, adjoint_solve=False, dyhat=None, lam=None):
+        """(dJ/dyhat field, dJ/dalpha, dJ/dbeta) at an ADMM solution."""
+        dab = (ctypes.c_double * 2)()
+        _check(lib().fde_grad(self._h, _dptr(yhat), _dptr(y), _dptr(p), _dptr(wy), int(adjoint_solve),
+                              _dptr(dyhat), dab, _dptr(lam)), False)
+        return dyhat, dab[0], dab[1]

@@ -1,0 +1,118 @@
+"""C-ABI library: exports, validation and the host-side setup tables (no GPU use).
+
+The host tables are compared with the oracle's independent dense construction
+(T. Chan columns by the closed form, eigenvalues by explicit DFT sums)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import grunwald, precond
+from oracle import operator as op
+from paper_1907_13428_amd import fde
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(not os.path.exists(fde.LIB_PATH), reason="libfde.so not built")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fde.h")).read()
+    return sorted(set(re.findall(r"\b(fde_[a-z_A-Z]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = fde.lib()
+    names = declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(fde.EXPORTED) == set(names)
+
+
+def test_version_and_empty_error():
+    assert b"gfx950" in fde.lib().fde_version()
+
+
+@pytest.mark.parametrize("field,value,frag", [
+    ("nx", 10, "nx=10"), ("ny", 2, "ny=2"), ("nt", 2048, "nt=2048"), ("alpha", 1.0, "alpha"),
+    ("beta", 2.5, "beta"), ("T", 0.0, "T must"), ("ctrl_sign", 0.5, "ctrl_sign"),
+    ("obj_weights", 3, "obj_weights"), ("precond_fp32", 2, "precond_fp32")])
+def test_problem_validation(field, value, frag):
+    w = W.small()
+    prob, prm = fde.from_workload(w)
+    setattr(prob, field, value)
+    with pytest.raises(fde.FdeError) as e:
+        fde.validate(prob, prm)
+    assert e.value.status == fde.FDE_EINVAL and frag in str(e.value)
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 0.0), ("delta", -1.0), ("rho", 1.7), ("rho", 0.0),
+                                         ("krylov_maxit", 0), ("admm_maxit", 0), ("tol_mode", 5),
+                                         ("ya", 1.0), ("ua", math.nan), ("krylov_tol", -1.0)])
+def test_param_validation(field, value):
+    w = W.small()
+    prob, prm = fde.from_workload(w)
+    if field == "ya":
+        prm.yb = 0.0
+    setattr(prm, field, value)
+    with pytest.raises(fde.FdeError):
+        fde.validate(prob, prm)
+
+
+def test_negative_coefficient_rejected():
+    w = W.small()
+    w.dplus = -np.ones((w.ny, w.nx))
+    prob, prm = fde.from_workload(w)
+    with pytest.raises(fde.FdeError):
+        fde.validate(prob, prm)
+
+
+def test_supported_sizes():
+    w = W.small()
+    for n in (4, 6, 8, 12, 16, 24, 48, 96, 192, 256, 384, 512, 768, 1024):
+        prob, prm = fde.from_workload(w.replace(nx=n, ny=n, nt=n, yhat=None))
+        fde.validate(prob, prm)
+    for n in (3, 5, 9, 18, 36, 1536, 2048):
+        prob, prm = fde.from_workload(w.replace(nx=n, yhat=None))
+        with pytest.raises(fde.FdeError):
+            fde.validate(prob, prm)
+
+
+@pytest.mark.parametrize("wl", ["small", "headline_small", "trap"])
+def test_host_tables_match_oracle(wl):
+    if wl == "small":
+        w = W.small()
+    elif wl == "headline_small":
+        w = W.headline(nx=24, ny=16, nt=8)
+    else:
+        w = W.small_mixed(nx=12, ny=8, nt=6, obj_weights=1, rho=1.618, delta=0.4)
+    prob, prm = fde.from_workload(w)
+    t = fde.host_tables(prob, prm)
+    d = op.disc_from(w)
+    tab = precond.precond_tables(w, d)
+    assert t["psi"] == pytest.approx(tab["psi"], rel=1e-15)
+    assert t["a"] == pytest.approx(tab["a"], rel=1e-14)
+    assert t["inv_mbar"] == pytest.approx(1.0 / tab["mbar_p"], rel=1e-14)
+    assert t["hx"] == d.hx and t["hy"] == d.hy and t["ht"] == pytest.approx(d.ht, rel=1e-15)
+    for k in ("lam_x", "lam_y", "lam_t"):
+        ref = tab[k]
+        assert np.max(np.abs(t[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+    np.testing.assert_allclose(t["gx"], grunwald.weights(w.alpha, w.nx), rtol=1e-15, atol=1e-300)
+    np.testing.assert_allclose(t["gy"], grunwald.weights(w.beta, w.ny), rtol=1e-15, atol=1e-300)
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding refuses to run without a GPU instead of falling back."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    w = W.small()
+    prob, prm = fde.from_workload(w)
+    with pytest.raises(RuntimeError):
+        fde.Context(prob, prm)
