@@ -1,0 +1,160 @@
+"""Benchmark: ADMM hot path on the 256^2 x 64 headline grid, one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-full] [--no-cpu]
+
+A step is one ADMM iteration of Algorithm 1 (right-hand side, the PCG solve
+of the normal equations, recovery of p and u, box projection, dual updates
+and residual maxima) over the synthetic headline workload: orders 1.3/1.7,
+d+ = 1 + 0.5 sin(2 pi x), d- = 1, yhat = 16 e^t x(1-x) y(1-y), gamma 1e-6,
+0 <= u <= 2, y <= 0.8, control as a source, delta = rho = 1, Krylov tol
+1e-10, ADMM tol 1e-6, FP64.  W untimed iterations from a cold start are
+followed by K timed ones; value = PCG iterations per second over the timed
+region (inputs resident in HBM).  The cold-start ADMM solve (tolerance 1e-6,
+iteration cap --full-cap) is timed as well, FP64 and with the FP32
+preconditioner; at this grid and delta = rho = 1 the ADMM residual on the
+control copy falls slowly, so the cap is normally reached and the record says
+so ("converged": false, residuals).  Each PCG pass is timed with HIP events
+for the roofline figure of the dominant kernel.  The
+CPU oracle's PCG iteration on the same grid is timed on a bounded sample.
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-full", action="store_true", help="skip the full cold-start solves")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--full-cap", type=int, default=1500,
+                    help="ADMM iteration cap of the cold-start solves (tolerance 1e-6)")
+    return ap.parse_args()
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, iters):
+    """The oracle's PCG (dense Toeplitz / dense DFT, FP64 NumPy) on the same grid:
+    `iters` iterations from a seeded right-hand side."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    import workloads as W
+    from oracle import admm, precond
+    from oracle import operator as op
+
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    tab = precond.precond_tables(w, d)
+    b = W.random_field(w.shape, 99)
+    t0 = time.perf_counter()
+    admm.pcg(lambda v: admm.apply_S(d, sc, v), lambda v: precond.apply_precond(tab, v), b, np.zeros(w.shape),
+             0.0, iters)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": iters / dt, "unit": "PCG iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{iters} PCG iterations of the oracle on the 256x256x64 headline grid "
+                      f"(S apply + no-FFT preconditioner), {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_1907_13428_amd import fde
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    w = W.headline()
+    yhat = torch.from_numpy(w.yhat).to("cuda")
+    out = {"metric": "PCG iters/s + ADMM solve time, 256^2x64 grid; HBM GB/s; FP32-precond vs FP64",
+           "unit": "PCG iters/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic"}
+
+    # ---- timed ADMM iterations (FP64) -------------------------------------
+    prob, prm = fde.from_workload(w, admm_tol=0.0, admm_maxit=max(a.warmup, 1))
+    ctx = fde.Context(prob, prm)
+    progress(f"warmup {a.warmup} ADMM iterations")
+    state, st_w, _ = ctx.admm_solve(yhat)
+    ctx.set_params(fde.from_workload(w, admm_tol=0.0, admm_maxit=a.steps)[1])
+    torch.cuda.synchronize()
+    progress(f"timing {a.steps} ADMM iterations")
+    t0 = time.perf_counter()
+    state, st, _ = ctx.admm_solve(yhat, state=state)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["value"] = st["pcg_total"] / dt
+    out["ms_per_step"] = 1e3 * dt / a.steps
+    out["pcg_per_admm_iter"] = st["pcg_total"] / a.steps
+
+    # ---- per-pass kernel timing (HIP events on the library stream) ---------
+    passes = {}
+    for i, name in enumerate(fde.PASS_NAMES):
+        us, by = ctx.time_pass(i, reps=50)
+        passes[name] = {"us": round(us, 2), "GB/s": round(by / us / 1e3, 1), "bytes": by}
+    dom = max(passes, key=lambda k: passes[k]["us"])
+    achieved = passes[dom]["bytes"] / passes[dom]["us"] / 1e3
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    pcg_pass_us = sum(p["us"] for p in passes.values())
+    pcg_bytes = sum(p["bytes"] for p in passes.values())
+    out["pcg_iteration_passes"] = passes
+    out["pcg_iteration_model"] = {"us": round(pcg_pass_us, 1), "GB": round(pcg_bytes / 1e9, 4),
+                                  "GB/s": round(pcg_bytes / pcg_pass_us / 1e3, 1)}
+    ctx.close()
+
+    # ---- full cold-start solves: FP64 and FP32 preconditioner ---------------
+    if not a.no_full:
+        for tag, fp32 in (("fp64", 0), ("fp32_precond", 1)):
+            progress(f"full ADMM solve ({tag})")
+            prob, prm = fde.from_workload(w, precond_fp32=fp32, admm_maxit=a.full_cap)
+            with fde.Context(prob, prm) as c2:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s2, st2, status = c2.admm_solve(yhat)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                if fp32 == 0:
+                    y64 = s2["y"].clone()
+                    u64 = s2["u"].clone()
+                rec = {"admm_solve_s": round(t, 3), "admm_iters": st2["admm_iters"], "admm_cap": a.full_cap,
+                       "pcg_total": st2["pcg_total"], "pcg_iters_per_s": round(st2["pcg_total"] / t, 1),
+                       "ms_per_admm_iter": round(1e3 * t / st2["admm_iters"], 3), "converged": status == 0,
+                       "residuals": [st2["r_p"], st2["r_y"], st2["r_u"]]}
+                if fp32:
+                    rec["rel_diff_y_vs_fp64"] = float(torch.linalg.norm(s2["y"] - y64) / torch.linalg.norm(y64))
+                    rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))
+                out[tag] = rec
+        out["admm_solve_s"] = out["fp64"]["admm_solve_s"]
+
+    out["config"] = {"workload": "headline_256x256x64", "nx": 256, "ny": 256, "nt": 64, "alpha": 1.3, "beta": 1.7,
+                     "gamma": 1e-6, "delta": 1.0, "rho": 1.0, "krylov_tol": 1e-10, "admm_tol": 1e-6,
+                     "precond": "fp64"}
+    if not a.no_cpu:
+        progress("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,8 @@ typedef struct {
   double ctrl_sign;       /* s = +1: D y + u = g (eq. (4.8)); -1: D y - u = g    */
   int32_t psi_scaling;    /* 1: scale the constraints by psi = min{ht, hx^alpha,
                              hy^beta} and the copies of u by psi (Sec. 5, 6.1);
-                             0: unscaled                                        */
+                             2: scale the FDE constraint only (u copies
+                             unscaled); 0: unscaled                             */
   int32_t obj_weights;    /* 0: J1 = I; 1: trapezoidal, 1/2 on the last time
                              block (eq. (4.10))                                 */
   int32_t precond_fp32;   /* 1: run the circulant preconditioner in float32
@@ -118,7 +119,9 @@ fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, 
 /* Create a context on the current HIP device.  `stream` is a hipStream_t
  * (NULL = default stream).  Validates, builds the weights, embedding and
  * T. Chan eigen tables and twiddles on the host (FP64), copies them to the
- * device and allocates the workspace.  *out receives the context. */
+ * device and allocates the workspace.  *out receives the context.  The PCG
+ * iteration is replayed from a HIP graph captured on a private stream
+ * (environment FDE_NO_GRAPH=1 at create time: plain kernel launches). */
 fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream,
                       fde_ctx** out);
 fde_status fde_destroy(fde_ctx* ctx);
@@ -176,6 +179,20 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
 fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const double* p,
                     const double* wy, int adjoint_solve, double* dyhat, double* dab,
                     double* lambda_out);
+
+/* Measurement hook for the roofline figure: launch one internal pass of the
+ * PCG iteration `reps` times back to back on the context stream between two
+ * HIP events and report the mean duration per launch (*us, host) and the
+ * algorithmic HBM bytes one launch must move (*bytes, host: every field the
+ * pass reads or writes counted once).  The pass runs on the context's
+ * workspace (contents are overwritten).  which:
+ *   0 x-pass of B (time difference fused)   1 y-pass of B (scaled by M_p^-1)
+ *   2 x-pass of B^T                          3 y-pass of B^T (+ M_y v, (v, Sv))
+ *   4 preconditioner x-forward (fused r -= alpha q, x += alpha p, (r, r))
+ *   5 preconditioner y-forward   6 t-forward/divide/t-inverse
+ *   7 preconditioner y-inverse   8 x-inverse (fused (r, z))
+ * Synchronises the stream. */
+fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes);
 
 /* Last error message of the calling thread ("" if none). */
 const char* fde_last_error(void);

@@ -59,7 +59,7 @@ def objective_weights(w) -> np.ndarray:
 def scalars(w, d: op.Disc) -> Scalars:
     psi = op.psi_scale(d) if w.psi_scaling else 1.0
     e_y = 1.0
-    e_u = psi if w.psi_scaling else 1.0
+    e_u = psi if w.psi_scaling == 1 else 1.0
     k_u = psi * w.ctrl_sign
     wts = objective_weights(w)
     My = w.rho * (wts + e_y ** 2 / w.delta)
@@ -133,6 +133,7 @@ class AdmmResult:
     r_u: float
     converged: bool
     psi: float
+    e_u: float = 1.0
 
 
 def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
@@ -205,7 +206,7 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
             converged = True
             break
     return AdmmResult(y=y, u=u, zy=zy, zu=zu, p=p, wy=wy, wu=wu, iters=j, pcg_iters=pcg_counts,
-                      r_p=r_p, r_y=r_y, r_u=r_u, converged=converged, psi=sc.psi)
+                      r_p=r_p, r_y=r_y, r_u=r_u, converged=converged, psi=sc.psi, e_u=sc.e_u)
 
 
 def xstep_block_solve(w, yhat, zy, zu, p, wy, wu, g=None):

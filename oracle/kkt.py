@@ -29,9 +29,9 @@ def objective(w, y, u) -> float:
 
 
 def multipliers(res):
-    """Unscaled multipliers from ADMM iterates: lambda = psi p, mu_y = w_y,
-    mu_u = psi w_u (e_y = 1, e_u = psi)."""
-    return res.psi * res.p, res.wy, res.psi * res.wu
+    """Unscaled multipliers from ADMM iterates: lambda = psi p, mu_y = e_y w_y,
+    mu_u = e_u w_u (e_y = 1; e_u = psi when the u copies are scaled)."""
+    return res.psi * res.p, res.wy, res.e_u * res.wu
 
 
 def kkt_residuals(w, y, u, lam, mu_y, mu_u, zy=None, zu=None):

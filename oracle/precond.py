@@ -75,7 +75,7 @@ def precond_tables(w, d: Disc):
     lam_t = dft_eigenvalues(col_t)
     psi = psi_scale(d) if w.psi_scaling else 1.0
     e_y = 1.0
-    e_u = psi if w.psi_scaling else 1.0
+    e_u = psi if w.psi_scaling == 1 else 1.0
     k_u = psi * w.ctrl_sign
     jbar = 1.0
     a = w.rho * (jbar + e_y ** 2 / w.delta)

@@ -10,6 +10,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -70,6 +71,14 @@ struct fde_ctx {
   double* h_scal = nullptr;  // pinned
   int* h_ints = nullptr;
   std::vector<void*> allocs;
+
+  // one PCG iteration captured as a HIP graph (re-captured when the
+  // solution pointer changes); launched on `stream`
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t pcg_graph = nullptr;
+  hipGraphExec_t pcg_exec = nullptr;
+  const double* pcg_graph_x = nullptr;
+  bool use_graph = true;
 
   template <typename T>
   hipError_t alloc(T** p, size_t count) {
@@ -223,6 +232,67 @@ fde_status sync_scalars(fde_ctx* c) {
   return FDE_OK;
 }
 
+// One PCG iteration (13 launches): q = S p ; alpha ; x += alpha p, r -= alpha q,
+// (r, r) and the convergence test ; z = S~^{-1} r ; (r, z) ; beta ; p = z + beta p.
+// Every kernel returns at once when the device flag says the solve is done.
+hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
+  using namespace fde;
+  const int* done = c->ints + kDone;
+  int nbS = 0, nb1 = 0, nb5 = 0;
+  hipError_t e;
+  if ((e = apply_S(c, c->pk, c->q, c->part_pq, done, &nbS)) != hipSuccess) return e;
+  if ((e = launch_pcg_scalar(FIN_ALPHA, c->part_pq, nbS, c->scal, c->ints, c->stream)) != hipSuccess) return e;
+  PrecondArgs a = pre_args(c, c->r, c->z);
+  a.q = c->q;
+  a.xvec = x;
+  a.pvec = c->pk;
+  a.partial = c->part_rr;
+  a.partial2 = c->part_rz;
+  a.done = done;
+  if ((e = launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5)) != hipSuccess) return e;
+  if ((e = launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream)) != hipSuccess) return e;
+  if ((e = launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5)) != hipSuccess) return e;
+  if ((e = launch_pcg_scalar(FIN_BETA, c->part_rz, nb5, c->scal, c->ints, c->stream)) != hipSuccess) return e;
+  return launch_axpy_dot(VEC_PUPDATE, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr);
+}
+
+void drop_pcg_graph(fde_ctx* c) {
+  if (c->pcg_exec) (void)hipGraphExecDestroy(c->pcg_exec);
+  if (c->pcg_graph) (void)hipGraphDestroy(c->pcg_graph);
+  c->pcg_exec = nullptr;
+  c->pcg_graph = nullptr;
+  c->pcg_graph_x = nullptr;
+}
+
+// capture one PCG iteration on the private capture stream
+fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
+  if (c->pcg_exec && c->pcg_graph_x == x) return FDE_OK;
+  drop_pcg_graph(c);
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = enqueue_pcg_iteration(c, x);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = user;
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return (fde_status)fail(FDE_EHIP, std::string("PCG graph capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e3 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return (fde_status)fail(FDE_EHIP, std::string("PCG graph instantiate: ") + hipGetErrorString(e3));
+  }
+  c->pcg_graph = g;
+  c->pcg_exec = ex;
+  c->pcg_graph_x = x;
+  return FDE_OK;
+}
+
 // PCG on S x = b (x: initial guess in, solution out).  Returns status; fills iters/relres.
 fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit, int* iters, double* relres,
                   int predict) {
@@ -230,7 +300,7 @@ fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit,
   const int* done = c->ints + kDone;
   // tolerance and iteration limit into device scalars
   const double tol2 = tol * tol;
-  int nbS = 0, nbv = 0, nb1 = 0, nb5 = 0;
+  int nbv = 0, nb1 = 0, nb5 = 0;
   // r = b - S x ; (r, r), (b, b)
   HIP_TRY(apply_S(c, x, c->q, nullptr, nullptr, nullptr));
   HIP_TRY(launch_axpy_dot(VEC_RESID, c->N, b, c->q, c->r, c->scal, c->part_pq, nullptr, c->stream, &nbv));
@@ -249,26 +319,17 @@ fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit,
   int enqueued = 0;
   int chunk = predict > 1 ? predict : 2;
   fde_status st = FDE_OK;
+  if (c->use_graph) {
+    st = ensure_pcg_graph(c, x);
+    if (st != FDE_OK) return st;
+  }
   while (true) {
     for (int k = 0; k < chunk && enqueued < maxit; ++k, ++enqueued) {
-      // q = S p ; alpha = (r,z)/(p,q)
-      HIP_TRY(apply_S(c, c->pk, c->q, c->part_pq, done, &nbS));
-      HIP_TRY(launch_pcg_scalar(FIN_ALPHA, c->part_pq, nbS, c->scal, c->ints, c->stream));
-      // x += alpha p ; r -= alpha q ; (r, r) ; convergence test ; z = S~^{-1} r ; (r, z) ; beta
-      PrecondArgs a = pre_args(c, c->r, c->z);
-      a.q = c->q;
-      a.xvec = x;
-      a.pvec = c->pk;
-      a.partial = c->part_rr;
-      a.partial2 = c->part_rz;
-      a.done = done;
-      HIP_TRY(launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5));
-      HIP_TRY(launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream));
-      HIP_TRY(launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5));
-      HIP_TRY(launch_pcg_scalar(FIN_BETA, c->part_rz, nb5, c->scal, c->ints, c->stream));
-      // p = z + beta p
-      HIP_TRY(launch_axpy_dot(VEC_PUPDATE, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream,
-                              nullptr));
+      if (c->use_graph) {
+        HIP_TRY(hipGraphLaunch(c->pcg_exec, c->stream));
+      } else {
+        HIP_TRY(enqueue_pcg_iteration(c, x));
+      }
     }
     if ((st = sync_scalars(c)) != FDE_OK) return st;
     if (c->h_ints[kDone] || enqueued >= maxit) break;
@@ -283,6 +344,9 @@ fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit,
 }
 
 fde_status free_all(fde_ctx* c) {
+  drop_pcg_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -331,6 +395,9 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   c->N = (int64_t)prob->nx * prob->ny * prob->nt;
   c->var = c->su.var;
   c->fp32 = prob->precond_fp32 != 0;
+  // FDE_NO_GRAPH=1 launches the PCG iteration kernel by kernel (no HIP graph)
+  const char* ng = std::getenv("FDE_NO_GRAPH");
+  c->use_graph = !(ng && ng[0] == '1');
   auto& s = c->su;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) {
@@ -657,6 +724,66 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   }
   dab[0] = out[0];
   dab[1] = out[1];
+  return FDE_OK;
+}
+
+fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes) {
+  using namespace fde;
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (which < 0 || which > 8 || reps <= 0) return (fde_status)fail(FDE_EINVAL, "fde_time_pass: bad pass or reps");
+  fde_ctx* c = ctx;
+  const size_t N = (size_t)c->N;
+  double* fields[] = {c->fa, c->fw, c->fb, c->q, c->r, c->z, c->pk, c->bvec};
+  for (double* f : fields) HIP_TRY(hipMemsetAsync(f, 0, N * sizeof(double), c->stream));
+  const size_t sb = (size_t)c->H * c->ny * c->nt * (c->fp32 ? 8 : 16);
+  HIP_TRY(hipMemsetAsync(c->spec, 0, sb, c->stream));
+  HIP_TRY(hipMemsetAsync(c->scal, 0, sizeof(double) * kNumScalars, c->stream));
+  const double psi = c->su.psi, sti = psi / c->su.ht;
+  const double f8 = 8.0 * (double)N;
+  double b = 0;
+  switch (which) {
+    case 0: case 2: b = 2 * f8; break;  // read v, write out
+    case 1: b = 3 * f8; break;          // read v, acc; write out
+    case 3: b = 4 * f8; break;          // read v, acc, extra; write out
+    case 4: b = 6 * f8 + (double)sb; break;  // read r, q, x, p; write r, x, spectrum
+    case 5: case 6: case 7: b = 2.0 * (double)sb; break;
+    case 8: b = 2 * f8 + (double)sb; break;  // read spectrum, r; write z
+  }
+  auto launch = [&]() -> hipError_t {
+    switch (which) {
+      case 0: return xpass(c, c->pk, c->fa, false, sti, -psi, nullptr);
+      case 1: return ypass(c, c->pk, c->fa, c->fw, false, -psi, c->invMp, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr);
+      case 2: return xpass(c, c->fw, c->fb, true, sti, -psi, nullptr);
+      case 3: return ypass(c, c->fw, c->fb, c->q, true, -psi, nullptr, c->pk, c->My, c->pk, c->part_pq, nullptr,
+                           nullptr);
+      default: {
+        PrecondArgs a = pre_args(c, c->r, c->z);
+        if (which == 4) {
+          a.q = c->q;
+          a.xvec = c->bvec;
+          a.pvec = c->pk;
+          a.partial = c->part_rr;
+        }
+        if (which == 8) a.partial2 = c->part_rz;
+        return launch_precond_stage(a, c->fp32, 10 + (which - 3), c->stream, nullptr, nullptr);
+      }
+    }
+  };
+  HIP_TRY(launch());  // warm
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, c->stream));
+  for (int i = 0; i < reps; ++i) HIP_TRY(launch());
+  HIP_TRY(hipEventRecord(e1, c->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (us) *us = 1000.0 * ms / reps;
+  if (bytes) *bytes = b;
   return FDE_OK;
 }
 

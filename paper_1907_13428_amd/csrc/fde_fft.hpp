@@ -11,6 +11,10 @@
 // transform thread t holds X[t + T*e].  A pointwise spectral product can
 // therefore be applied in registers and followed directly by the inverse.
 //
+// When the T threads of a line lie in one wavefront (T <= 64) the LDS
+// exchanges are ordered by wavefront-scope fences instead of block barriers,
+// so independent lines in one block never wait for each other.
+//
 // The FFT is the O(N log N) primitive of Table 1 (Sec. 5): the Toeplitz
 // products use it through a 2n circulant embedding, the multilevel circulant
 // preconditioner through plain length-n transforms per axis.
@@ -75,18 +79,27 @@ template <int SIGN, typename V> struct Dft<4, SIGN, V> {
   }
 };
 
+// multiply by exp(SIGN i pi k / 4) for k = 1, 3 (k = 2 is SIGN i)
+template <int SIGN, typename V> __device__ __forceinline__ V rot8_1(V o) {
+  using R = decltype(o.x);
+  const R r2 = R(0.7071067811865475244008443621048490392848);
+  return V{(o.x - SIGN * o.y) * r2, (o.y + SIGN * o.x) * r2};
+}
+template <int SIGN, typename V> __device__ __forceinline__ V rot8_3(V o) {
+  using R = decltype(o.x);
+  const R r2 = R(0.7071067811865475244008443621048490392848);
+  return V{(-o.x - SIGN * o.y) * r2, (-o.y + SIGN * o.x) * r2};
+}
+
 template <int SIGN, typename V> struct Dft<8, SIGN, V> {
   __device__ __forceinline__ static void run(V* a) {
-    using R = decltype(a[0].x);
-    const R r2 = R(0.7071067811865475244008443621048490392848);  // 1/sqrt(2)
     V e[4] = {a[0], a[2], a[4], a[6]};
     V o[4] = {a[1], a[3], a[5], a[7]};
     Dft<4, SIGN, V>::run(e);
     Dft<4, SIGN, V>::run(o);
-    // o_k *= exp(SIGN i pi k / 4)
-    V o1 = V{(o[1].x - SIGN * o[1].y) * r2, (o[1].y + SIGN * o[1].x) * r2};
-    V o2 = cmul_si<SIGN>(o[2]);
-    V o3 = V{(-o[3].x - SIGN * o[3].y) * r2, (-o[3].y + SIGN * o[3].x) * r2};
+    const V o1 = rot8_1<SIGN>(o[1]);
+    const V o2 = cmul_si<SIGN>(o[2]);
+    const V o3 = rot8_3<SIGN>(o[3]);
     a[0] = cadd(e[0], o[0]);
     a[4] = csub(e[0], o[0]);
     a[1] = cadd(e[1], o1);
@@ -98,20 +111,71 @@ template <int SIGN, typename V> struct Dft<8, SIGN, V> {
   }
 };
 
+// 16 = 4 x 4: DFT-4 over m1 (inputs 4 m1 + m2), twiddle w16^{m2 k1}, DFT-4 over m2
+template <int SIGN, typename V> struct Dft<16, SIGN, V> {
+  __device__ __forceinline__ static void run(V* a) {
+    using R = decltype(a[0].x);
+    const R c1 = R(0.9238795325112867561281831893967882868224);  // cos(pi/8)
+    const R s1 = R(0.3826834323650897717284599840303988667613);  // sin(pi/8)
+    V b[4][4];
+#pragma unroll
+    for (int m2 = 0; m2 < 4; ++m2) {
+      V col[4] = {a[m2], a[4 + m2], a[8 + m2], a[12 + m2]};
+      Dft<4, SIGN, V>::run(col);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) b[m2][k1] = col[k1];
+    }
+    // twiddles w16^{m2 k1} = exp(SIGN 2 pi i m2 k1 / 16)
+#pragma unroll
+    for (int m2 = 1; m2 < 4; ++m2) {
+#pragma unroll
+      for (int k1 = 1; k1 < 4; ++k1) {
+        const int p = (m2 * k1) & 15;  // 1, 2, 3, 4, 6, 9
+        V x = b[m2][k1];
+        V r;
+        switch (p) {
+          case 1: r = V{x.x * c1 - SIGN * x.y * s1, x.y * c1 + SIGN * x.x * s1}; break;
+          case 2: r = rot8_1<SIGN>(x); break;
+          case 3: r = V{x.x * s1 - SIGN * x.y * c1, x.y * s1 + SIGN * x.x * c1}; break;
+          case 4: r = cmul_si<SIGN>(x); break;
+          case 6: r = rot8_3<SIGN>(x); break;
+          default: /* 9: exp(SIGN i 9 pi/8) = -cos(pi/8) - SIGN i sin(pi/8) */
+            r = V{-x.x * c1 + SIGN * x.y * s1, -x.y * c1 - SIGN * x.x * s1};
+            break;
+        }
+        b[m2][k1] = r;
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      V row[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+      Dft<4, SIGN, V>::run(row);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = row[k2];
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
-// radix plan: stage radices from {8, 4, 3, 2}, each dividing E
+// radix plan: stage radices from {16, 8, 4, 3, 2}, each dividing E
 // ---------------------------------------------------------------------------
 constexpr int pick_radix(int rem, int E) {
-  return (rem % 8 == 0 && E % 8 == 0) ? 8
+  return (rem % 16 == 0 && E % 16 == 0) ? 16
+         : (rem % 8 == 0 && E % 8 == 0) ? 8
          : (rem % 4 == 0 && E % 4 == 0) ? 4
          : (rem % 3 == 0 && E % 3 == 0) ? 3
          : (rem % 2 == 0 && E % 2 == 0) ? 2
                                         : 0;
 }
 
-// elements per thread for a line of length L
+// elements per thread for a line of length L (radix-16 stages for 128 and
+// 256 points; 8 elements elsewhere, so that long lines keep their register
+// footprint low and use 2 or 4 wavefronts with block barriers)
 constexpr int default_E(int L) {
-  return (L % 3 == 0) ? (L >= 24 ? 24 : L) : (L >= 8 ? 8 : L);
+  return (L % 3 == 0) ? (L >= 24 ? 24 : L)
+         : (L <= 16)  ? L
+         : (L == 128 || L == 256) ? 16
+                                  : 8;
 }
 
 // padded LDS index: one spare slot per 8 keeps power-of-two strides off a bank
@@ -125,6 +189,64 @@ template <typename V> struct LineLds {
   __device__ __forceinline__ V& operator[](int i) const { return base[lpad(i) * rs]; }
 };
 
+// Ordering of an LDS exchange among the threads of one line.
+template <bool WAVE> __device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// twiddles w^m, m = 1..R-1, w = exp(SIGN 2 pi i j / (Ls R)), from a few table
+// loads (powers of two of w) and complex products
+template <int R, int SIGN, typename V>
+__device__ __forceinline__ void stage_twiddles(V (&w)[R], const V* __restrict__ tw, int idx) {
+  auto ld = [&](int k) {
+    V x = tw[k];
+    if (SIGN > 0) x.y = -x.y;
+    return x;
+  };
+  w[0] = V{1, 0};
+  if constexpr (R == 2) {
+    w[1] = ld(idx);
+  } else if constexpr (R == 3) {
+    w[1] = ld(idx);
+    w[2] = ld(2 * idx);
+  } else if constexpr (R == 4) {
+    w[1] = ld(idx);
+    w[2] = ld(2 * idx);
+    w[3] = cmul(w[1], w[2]);
+  } else if constexpr (R == 8) {
+    w[1] = ld(idx);
+    w[2] = ld(2 * idx);
+    w[4] = ld(4 * idx);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+  } else {
+    static_assert(R == 16, "radix");
+    w[1] = ld(idx);
+    w[2] = ld(2 * idx);
+    w[4] = ld(4 * idx);
+    w[8] = ld(8 * idx);
+    w[3] = cmul(w[1], w[2]);
+    w[5] = cmul(w[4], w[1]);
+    w[6] = cmul(w[4], w[2]);
+    w[7] = cmul(w[4], w[3]);
+    w[9] = cmul(w[8], w[1]);
+    w[10] = cmul(w[8], w[2]);
+    w[11] = cmul(w[8], w[3]);
+    w[12] = cmul(w[8], w[4]);
+    w[13] = cmul(w[8], w[5]);
+    w[14] = cmul(w[8], w[6]);
+    w[15] = cmul(w[8], w[7]);
+  }
+}
+
 template <int L, int E, int Ls, int SIGN, typename V>
 struct Stages {
   static constexpr int rem = L / Ls;
@@ -133,9 +255,9 @@ struct Stages {
   static constexpr int T = L / E;
   static constexpr int Q = E / R;
   static constexpr bool LAST = (Ls * R == L);
+  static constexpr bool WAVE = (T <= 64);
 
   __device__ __forceinline__ static void run(V (&v)[E], LineLds<V> lds, int t, const V* __restrict__ tw) {
-    V out[E];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int b = t + T * q;
@@ -144,31 +266,27 @@ struct Stages {
       V x[R];
 #pragma unroll
       for (int m = 0; m < R; ++m) x[m] = v[q + m * Q];
-      if (Ls > 1) {
+      if constexpr (Ls > 1) {
+        V w[R];
+        stage_twiddles<R, SIGN>(w, tw, j * (L / (Ls * R)));
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-          V w = tw[j * m * (L / (Ls * R))];
-          if (SIGN > 0) w.y = -w.y;
-          x[m] = cmul(x[m], w);
-        }
+        for (int m = 1; m < R; ++m) x[m] = cmul(x[m], w[m]);
       }
       Dft<R, SIGN, V>::run(x);
-      if (LAST) {
+      if constexpr (LAST) {
+        // butterfly q reads and writes the same registers q + m*Q
 #pragma unroll
-        for (int m = 0; m < R; ++m) out[q + m * Q] = x[m];
+        for (int m = 0; m < R; ++m) v[q + m * Q] = x[m];
       } else {
 #pragma unroll
         for (int m = 0; m < R; ++m) lds[k * Ls * R + j + m * Ls] = x[m];
       }
     }
-    if constexpr (LAST) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = out[e];
-    } else {
-      __syncthreads();
+    if constexpr (!LAST) {
+      line_sync<WAVE>();
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = lds[t + T * e];
-      __syncthreads();
+      line_sync<WAVE>();
       Stages<L, E, Ls * R, SIGN, V>::run(v, lds, t, tw);
     }
   }
@@ -182,11 +300,16 @@ struct Stages<L, E, L, SIGN, V> {
 
 // Unnormalised DFT of the line held as v[e] = x[t + T e]; afterwards
 // v[e] = X[t + T e].  SIGN = -1 forward, +1 inverse.  `tw` is the length-L
-// table exp(-2 pi i m / L).  Every thread of the block must call it (it
-// contains block barriers when L needs more than one stage).
+// table exp(-2 pi i m / L).  With more than 64 threads per line every thread
+// of the block must call it (block barriers); otherwise every lane of the
+// line's wavefront must.
 template <int L, int E, int SIGN, typename V>
 __device__ __forceinline__ void line_fft(V (&v)[E], LineLds<V> lds, int t, const V* __restrict__ tw) {
   Stages<L, E, 1, SIGN, V>::run(v, lds, t, tw);
 }
+
+// true when a block of `threads` threads running lines of T threads needs
+// block-wide barriers inside line_fft
+template <int L> constexpr bool line_needs_block_sync() { return (L / default_E(L)) > 64; }
 
 }  // namespace fde

@@ -76,7 +76,7 @@ struct PrecondArgs {
   const int* done;
 };
 
-// stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5
+// stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5; 11..15: pass 1..5 alone
 hipError_t launch_precond_stage(const PrecondArgs& a, bool fp32, int stage, hipStream_t s, int* nb_fwd,
                                 int* nb_inv);
 inline hipError_t launch_precond(const PrecondArgs& a, bool fp32, hipStream_t s, int* nb_fwd, int* nb_inv) {

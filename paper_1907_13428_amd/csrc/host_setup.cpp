@@ -66,7 +66,7 @@ int validate(const fde_problem* p, const fde_admm_params* q, std::string* msg) {
   if (!(p->alpha > 1.0 && p->alpha <= 2.0)) { *msg = fmt("alpha=%g outside (1, 2]", p->alpha); return FDE_EINVAL; }
   if (!(p->beta > 1.0 && p->beta <= 2.0)) { *msg = fmt("beta=%g outside (1, 2]", p->beta); return FDE_EINVAL; }
   if (p->ctrl_sign != 1.0 && p->ctrl_sign != -1.0) { *msg = "ctrl_sign must be +1 or -1"; return FDE_EINVAL; }
-  if (p->psi_scaling != 0 && p->psi_scaling != 1) { *msg = "psi_scaling must be 0 or 1"; return FDE_EINVAL; }
+  if (p->psi_scaling < 0 || p->psi_scaling > 2) { *msg = "psi_scaling must be 0, 1 or 2"; return FDE_EINVAL; }
   if (p->obj_weights != 0 && p->obj_weights != 1) { *msg = "obj_weights must be 0 or 1"; return FDE_EINVAL; }
   if (p->precond_fp32 != 0 && p->precond_fp32 != 1) { *msg = "precond_fp32 must be 0 or 1"; return FDE_EINVAL; }
   const size_t plane = (size_t)p->nx * p->ny;
@@ -274,7 +274,7 @@ int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::s
   // psi = min{ht, hx^alpha, hy^beta} (Sec. 5 with time order 1)
   s->psi = p->psi_scaling ? std::fmin(s->ht, std::fmin(std::pow(hx, p->alpha), std::pow(hy, p->beta))) : 1.0;
   s->e_y = 1.0;
-  s->e_u = p->psi_scaling ? s->psi : 1.0;
+  s->e_u = (p->psi_scaling == 1) ? s->psi : 1.0;
   s->k_u = s->psi * p->ctrl_sign;
   s->obj_weights = p->obj_weights;
   set_admm_scalings(q, s);

@@ -107,9 +107,12 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
 template <int L> struct CCfg {
   static constexpr int E = default_E(L);
   static constexpr int T = L / E;
-  static constexpr int P = (kPreThreads / T) > 16 ? 16 : (kPreThreads / T);
+  static constexpr int cap(int a, int b) { return a < b ? a : b; }
+  // complex columns per block: at most 16, at most 256 threads, LDS tile within 128 KiB (FP64)
+  static constexpr int P = cap(cap(16, kPreThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
   static constexpr int NT = ((P * T + 63) / 64) * 64;
   static constexpr int RS = P + 1;
+  static_assert(P >= 1, "tile");
 };
 
 // MODE 0: y-direction, sign SIGN.  MODE 1: t-direction with the eigenvalue division.
@@ -285,8 +288,30 @@ static hipError_t pre_t(const PrecondArgs& a, hipStream_t s) {
 }
 
 template <typename TS>
+static hipError_t single_pass(const PrecondArgs& a, int pass, hipStream_t s) {
+  hipError_t err = hipErrorInvalidValue;
+  const int L = (pass == 1 || pass == 5) ? a.nx : (pass == 3 ? a.nt : a.ny);
+  switch (L) {
+#define CASE(Lv)                                                   \
+  case Lv:                                                         \
+    if (pass == 1) err = pre_x<Lv, TS>(a, true, s, nullptr);       \
+    else if (pass == 2) err = pre_y<Lv, TS>(a, -1, s);             \
+    else if (pass == 3) err = pre_t<Lv, TS>(a, s);                 \
+    else if (pass == 4) err = pre_y<Lv, TS>(a, +1, s);             \
+    else if (pass == 5) err = pre_x<Lv, TS>(a, false, s, nullptr); \
+    break;
+    FDE_FOR_DIM_LENGTHS(CASE)
+#undef CASE
+    default:
+      break;
+  }
+  return err;
+}
+
+template <typename TS>
 static hipError_t precond_T(const PrecondArgs& a, int stage, hipStream_t s, int* nb_fwd, int* nb_inv) {
   hipError_t err = hipSuccess;
+  if (stage >= 11 && stage <= 15) return single_pass<TS>(a, stage - 10, s);
   // pass 1 (x forward); partial sums of r.r only when fused
   if (stage != 2) {
     switch (a.nx) {

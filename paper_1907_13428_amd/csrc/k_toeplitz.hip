@@ -123,9 +123,12 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
 template <int L> struct YCfg {
   static constexpr int E = default_E(L);
   static constexpr int T = L / E;
-  static constexpr int P = (kLineThreads / T) > 8 ? 8 : (kLineThreads / T);  // column pairs per block
-  static constexpr int NT = ((P * T + 63) / 64) * 64;                       // threads per block
-  static constexpr int RS = P + 1;                                          // LDS row stride
+  static constexpr int cap(int a, int b) { return a < b ? a : b; }
+  // column pairs per block: at most 8, at most 256 threads, LDS tile within 128 KiB
+  static constexpr int P = cap(cap(8, kLineThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  static constexpr int NT = ((P * T + 63) / 64) * 64;  // threads per block
+  static constexpr int RS = P + 1;                     // LDS row stride (spare column P)
+  static_assert(P >= 1, "tile");
 };
 
 template <int L, bool VAR, bool TRANS>

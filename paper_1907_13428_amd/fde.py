@@ -22,8 +22,11 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
            -4: "FDE_ENONFINITE"}
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
-            "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_last_error",
-            "fde_version"]
+            "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_time_pass",
+            "fde_last_error", "fde_version"]
+
+PASS_NAMES = ["xpass_B", "ypass_B", "xpass_BT", "ypass_BT", "pre_xfwd", "pre_yfwd", "pre_t_div", "pre_yinv",
+              "pre_xinv"]
 
 
 class FdeError(RuntimeError):
@@ -79,6 +82,7 @@ def lib():
         L.fde_krylov.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
+        L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
         L.fde_last_error.restype = ctypes.c_char_p
         L.fde_version.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -233,6 +237,13 @@ class Context:
         status = _check(lib().fde_admm_solve(self._h, _dptr(yhat, "yhat"), _dptr(g, "g"), *args,
                                              ctypes.byref(st)))
         return state, st.as_dict(), status
+
+    def time_pass(self, which, reps=20):
+        """(mean microseconds per launch, algorithmic bytes per launch) of pass `which`."""
+        us = ctypes.c_double()
+        b = ctypes.c_double()
+        _check(lib().fde_time_pass(self._h, int(which), int(reps), ctypes.byref(us), ctypes.byref(b)), False)
+        return us.value, b.value
 
     def grad(self, yhat, y, p, wy=None, adjoint_solve=False, dyhat=None, lam=None):
         """(dJ/dyhat field, dJ/dalpha, dJ/dbeta) at an ADMM solution."""

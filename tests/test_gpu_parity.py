@@ -238,3 +238,27 @@ def test_gradients_match_oracle_formula():
     assert rel(dyh, gy) <= 1e-14
     assert abs(da - ga) <= 1e-10 * abs(ga), (da, ga)
     assert abs(db - gb) <= 1e-10 * abs(gb), (db, gb)
+
+
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """The PCG iteration replayed from a HIP graph gives bitwise the results
+    of kernel-by-kernel launches, over several solves with eager work between."""
+    banner("graph vs eager")
+    w = make("headline_24x16x8")
+    outs = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("FDE_NO_GRAPH", mode)
+        prob, prm = fde.from_workload(w)
+        with fde.Context(prob, prm) as ctx:
+            res = []
+            x = zeros(w.shape)
+            for k in range(3):
+                b = dev(W.random_field(w.shape, 30 + k))
+                it, _, st = ctx.krylov(b, x)
+                y = zeros(w.shape)
+                ctx.apply_A(x, y)  # eager work between replays
+                res.append((it, host(x), host(y)))
+            outs[mode] = res
+    for (i1, x1, y1), (i0, x0, y0) in zip(outs["1"], outs["0"]):
+        assert i1 == i0
+        assert np.array_equal(x1, x0) and np.array_equal(y1, y0)

@@ -50,7 +50,7 @@ class Workload:
     krylov_maxit: int = 1000
     admm_tol: float = 1e-6
     admm_maxit: int = 100000
-    psi_scaling: int = 1
+    psi_scaling: int = 1  # 1: B and the u copies scaled by psi; 2: B only; 0: none
     obj_weights: int = 0  # 0: all ones, 1: trapezoidal in time (eq. 4.10)
     yhat: Optional[np.ndarray] = None  # (nt, ny, nx)
     dplus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
