@@ -97,6 +97,8 @@ typedef struct {
   double r_p;             /* ||B y + k_u u - psi g||_inf  (scaled constraint)     */
   double r_y;             /* ||y - z_y||_inf                                      */
   double r_u;             /* ||u - z_u||_inf                                      */
+  double J;               /* objective 1/2 (y-yhat)^T J1 (y-yhat) + 1/2 u^T J2 u at
+                             the returned iterate                                */
   double t_total;         /* seconds, wall clock of the solve                    */
   double t_pcg;           /* seconds spent in the Krylov solves (host clock)     */
 } fde_admm_stats;
@@ -168,14 +170,19 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
 
 /* Gradients of the optimal value J*(yhat, alpha, beta) at an ADMM solution
  * (envelope theorem on the Lagrangian of eq. (3.5)):
- *   dJ/dyhat = -J1 (y - yhat)                       -> dyhat (device field)
+ *   dJ/dyhat = -J1 (y - yhat)                       -> dyhat (device field, may be NULL)
  *   dJ/dalpha = lambda^T (dD/dalpha) y, dJ/dbeta likewise -> dab[2] (host)
- * lambda is obtained by the adjoint solve D^T lambda = -J1 (y - yhat) - wy
- * (backward time stepping of the transposed operator, whose Toeplitz
- * products use the reversed weights; each step by preconditioned Krylov),
- * when adjoint_solve = 1, or taken as psi * p when adjoint_solve = 0.
- * dD/dalpha uses the derivative of the Grünwald recurrence.  lambda_out
- * (device field, may be NULL) receives lambda.  Synchronises. */
+ * with dD/dalpha = -dL_x/dalpha built from the derivative of the Grünwald
+ * recurrence (and of c_a h^-a).  lambda, the multiplier of D y + s u = g:
+ *   adjoint_solve = 1: from the adjoint equation D^T lambda = -J1 (y - yhat)
+ *     - wy, solved by backward time stepping (the transposed time difference
+ *     is upper bidiagonal); each step is a 2-D transposed-Toeplitz solve
+ *     (reversed weights) by BiCGSTAB preconditioned with the inverse of the
+ *     transposed 2-D T. Chan circulant, to 1e-13 relative residual;
+ *   adjoint_solve = 0: lambda = psi p from the ADMM iterate.
+ * wy may be NULL when adjoint_solve = 0.  lambda_out (device field, may be
+ * NULL) receives lambda.  Uses the context workspace.  Synchronises.
+ * FDE_ENOTCONV if a time step's solve does not converge in 500 iterations. */
 fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const double* p,
                     const double* wy, int adjoint_solve, double* dyhat, double* dab,
                     double* lambda_out);

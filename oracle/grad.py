@@ -53,13 +53,16 @@ def gradients(w, y, lam):
     return dyhat, dalpha, dbeta
 
 
-def adjoint_multiplier(w, y, mu_y):
+def adjoint_multiplier(w, y, mu_y, method="lu"):
     """lambda from the adjoint (transposed) state equation
-    D^T lambda = -J1 (y - yhat) - mu_y, solved with a sparse LU (small grids)."""
-    import scipy.sparse.linalg as spla
-
+    D^T lambda = -J1 (y - yhat) - mu_y: sparse LU of D^T ("lu"), or backward
+    time stepping with a dense LU of the 2-D block ("steps"); small grids."""
     d = op.disc_from(w)
-    D = op.assemble_D_sparse(d)
     J1 = tcol(objective_weights(w))
     rhs = (-J1 * (y - w.yhat) - mu_y).ravel()
+    if method == "steps":
+        return op.DSolver(d).solve(rhs, trans=True).reshape(w.shape)
+    import scipy.sparse.linalg as spla
+
+    D = op.assemble_D_sparse(d)
     return spla.spsolve(D.T.tocsc(), rhs).reshape(w.shape)

@@ -55,7 +55,7 @@ def kkt_residuals(w, y, u, lam, mu_y, mu_u, zy=None, zu=None):
     )
 
 
-def polish(w, zy, zu, tol=1e-9):
+def polish(w, zy, zu, tol=1e-9, method="auto"):
     """Exact optimum on the active set read off the z-iterates.
 
     Components of z at a finite bound are fixed there; the remaining
@@ -88,6 +88,10 @@ def polish(w, zy, zu, tol=1e-9):
     Au = np.nonzero(ulo | uhi)[0]
     by = np.where(ylo[Ay], w.ya, w.yb) if len(Ay) else np.zeros(0)
     bu = np.where(ulo[Au], w.ua, w.ub) if len(Au) else np.zeros(0)
+    nfree = N - len(Au)
+    if method == "reduced" or (method == "auto" and nfree + len(Ay) <= 1500 and w.nx * w.ny <= 4096):
+        y, u, lam, my, mu = _polish_reduced(d, J1, w.gamma, s, g, w.yhat.ravel(), Au, bu, Ay, by)
+        return _finish(w, y, u, lam, my, mu, ylo, yhi, ulo, uhi, tol)
     Ey = sp.csr_matrix((np.ones(len(Ay)), (np.arange(len(Ay)), Ay)), shape=(len(Ay), N))
     Eu = sp.csr_matrix((np.ones(len(Au)), (np.arange(len(Au)), Au)), shape=(len(Au), N))
     Z = lambda m, n: sp.csr_matrix((m, n))
@@ -107,6 +111,43 @@ def polish(w, zy, zu, tol=1e-9):
     mu = np.zeros(N)
     my[Ay] = sol[3 * N:3 * N + len(Ay)]
     mu[Au] = sol[3 * N + len(Ay):]
+    return _finish(w, y, u, lam, my, mu, ylo, yhi, ulo, uhi, tol)
+
+
+def _polish_reduced(d, J1, gamma, s, g, yhat, Au, bu, Ay, by):
+    """The same equality-constrained QP with y = D^{-1}(g - s u) eliminated:
+    unknowns are the free controls u_F and the multipliers nu of the fixed
+    states; D is solved directly by time stepping (op.DSolver)."""
+    N = d.nx * d.ny * d.nt
+    lu = op.DSolver(d)
+    F = np.setdiff1d(np.arange(N), Au)
+    uA = np.zeros(N)
+    uA[Au] = bu
+    c = lu.solve(g - s * uA)  # y for u_F = 0
+    EF = np.zeros((N, len(F)))
+    EF[F, np.arange(len(F))] = 1.0
+    K = -s * lu.solve(EF)  # K = -s D^{-1} E_F^T
+    H = K.T @ (J1[:, None] * K) + np.diag(gamma * J1[F])
+    rhs1 = -K.T @ (J1 * (c - yhat))
+    if len(Ay):
+        KA = K[Ay, :]
+        M = np.block([[H, KA.T], [KA, np.zeros((len(Ay), len(Ay)))]])
+        sol = np.linalg.solve(M, np.concatenate([rhs1, by - c[Ay]]))
+        uF, nu = sol[:len(F)], sol[len(F):]
+    else:
+        uF, nu = np.linalg.solve(H, rhs1), np.zeros(0)
+    u = uA.copy()
+    u[F] = uF
+    y = c + K @ uF
+    my = np.zeros(N)
+    my[Ay] = nu
+    lam = -lu.solve(J1 * (y - yhat) + my, trans=True)
+    mu = np.zeros(N)
+    mu[Au] = -(gamma * J1[Au] * u[Au] + s * lam[Au])
+    return y, u, lam, my, mu
+
+
+def _finish(w, y, u, lam, my, mu, ylo, yhi, ulo, uhi, tol):
     feas = (np.all(y >= w.ya - tol) and np.all(y <= w.yb + tol)
             and np.all(u >= w.ua - tol) and np.all(u <= w.ub + tol))
     signs = (np.all(my[ylo] <= tol) and np.all(my[yhi] >= -tol)

@@ -149,6 +149,46 @@ def assemble_D_sparse(d: Disc):
     return (sp.kron(Ct, sp.identity(M)) - sp.kron(sp.identity(nt), Lx + Ly)).tocsr()
 
 
+class DSolver:
+    """Direct solves with D and D^T by time stepping (D is block lower
+    bidiagonal: diagonal blocks A = I/h_t - (L_x (+) L_y), sub-diagonal
+    -I/h_t), with one dense LU of the 2-D block A.  Right-hand sides are
+    (N,) or (N, m) arrays in the (t*ny + j)*nx + i ordering."""
+
+    def __init__(self, d: Disc):
+        import scipy.linalg as sla
+
+        self.d = d
+        M = d.nx * d.ny
+        Lx = np.zeros((M, M))
+        Ly = np.zeros((M, M))
+        for j in range(d.ny):
+            Lx[j * d.nx:(j + 1) * d.nx, j * d.nx:(j + 1) * d.nx] = line_matrix(
+                d.alpha, d.hx, d.nx, d.dplus[j, :], d.dminus[j, :])
+        for i in range(d.nx):
+            idx = np.arange(d.ny) * d.nx + i
+            Ly[np.ix_(idx, idx)] = line_matrix(d.beta, d.hy, d.ny, d.dplus[:, i], d.dminus[:, i])
+        A = np.eye(M) / d.ht - Lx - Ly
+        self.lu = sla.lu_factor(A)
+        self.M = M
+
+    def solve(self, f, trans=False):
+        import scipy.linalg as sla
+
+        d, M = self.d, self.M
+        f = np.asarray(f, dtype=np.float64)
+        shp = f.shape
+        F = f.reshape(d.nt, M, -1)
+        X = np.empty_like(F)
+        order = range(d.nt - 1, -1, -1) if trans else range(d.nt)
+        prev = None
+        for k in order:
+            rhs = F[k] if prev is None else F[k] + prev / d.ht
+            X[k] = sla.lu_solve(self.lu, rhs, trans=1 if trans else 0)
+            prev = X[k]
+        return X.reshape(shp)
+
+
 def psi_scale(d: Disc) -> float:
     """psi = min{h_t, h_x^alpha, h_y^beta} (Sec. 5, time order 1)."""
     return min(d.ht, d.hx ** d.alpha, d.hy ** d.beta)

@@ -64,7 +64,10 @@ struct fde_ctx {
   double *q = nullptr, *r = nullptr, *z = nullptr, *pk = nullptr, *bvec = nullptr;
   double *ar = nullptr, *Ru = nullptr, *av = nullptr, *ac = nullptr, *By = nullptr;
   void* spec = nullptr;
-  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_max = nullptr;
+  double *part_pq = nullptr, *part_rr = nullptr, *part_rz = nullptr, *part_max = nullptr, *part_dots = nullptr;
+  // adjoint time stepping: the 1-point "time" tables of a single-slice problem
+  double2* adj_lt = nullptr;
+  void* adj_twt = nullptr;
   int maxpart = 0;
   double* scal = nullptr;
   int* ints = nullptr;
@@ -367,10 +370,152 @@ fde_status upload_admm_tables(fde_ctx* c) {
   return FDE_OK;
 }
 
-// D^T lambda = -J1 (y - yhat) - wy  (adjoint state equation)
+// ---------------------------------------------------------------------------
+// Adjoint state equation D^T lambda = f, f = -J1 (y - yhat) - wy.
+// D^T = E^T - L_x^T - L_y^T with E^T upper bidiagonal in time, so lambda is
+// found by backward time stepping: lambda_{nt} = 0 and for k = nt-1 .. 0
+//     A^T lambda_k = f_k + lambda_{k+1} / h_t,   A = I/h_t - L_x - L_y,
+// a 2-D problem whose transposed Toeplitz products run the weights reversed
+// (G^T for G).  Each step: BiCGSTAB, right-preconditioned by the inverse of
+// the transposed 2-D T. Chan circulant (eigenvalues conj(1/h_t - lx - ly)),
+// warm-started from lambda_{k+1}.
+// ---------------------------------------------------------------------------
+struct SliceOps {
+  fde_ctx* c;
+  int64_t plane;
+  // y = A^T x on one slice
+  hipError_t applyAT(const double* x, double* y) {
+    fde::LinePassArgs a = line_args(c);
+    a.nt = 1;
+    a.in = x;
+    a.out = c->fa;
+    a.tw = c->twx_emb;
+    a.lamA = c->lxTA;
+    a.lamB = c->lxTB;
+    a.s_time = 1.0 / c->su.ht;
+    a.s_sp = -1.0;
+    hipError_t e = fde::launch_xpass(a, true, c->var, c->stream, nullptr);
+    if (e != hipSuccess) return e;
+    fde::LinePassArgs b = line_args(c);
+    b.nt = 1;
+    b.in = x;
+    b.acc = c->fa;
+    b.out = y;
+    b.tw = c->twy_emb;
+    b.lamA = c->lyTA;
+    b.lamB = c->lyTB;
+    b.s_sp = -1.0;
+    return fde::launch_ypass(b, true, c->var, c->stream, nullptr);
+  }
+  // z = C(A)^{-T} r on one slice
+  hipError_t precond(double* r, double* z) {
+    fde::PrecondArgs a = pre_args(c, r, z);
+    a.nt = 1;
+    a.twt = c->adj_twt;
+    a.lam_t = c->adj_lt;
+    a.psi = 1.0;
+    a.inv_n = 1.0 / (double)plane;
+    a.div_mode = 1;
+    return fde::launch_precond(a, c->fp32, c->stream, nullptr, nullptr);
+  }
+  hipError_t dots(int count, const double* const* a, const double* const* b) {
+    return fde::launch_dots(plane, count, a, b, c->part_dots, c->scal, c->stream);
+  }
+};
+
+fde_status read_dots(fde_ctx* c, double* out, int count) {
+  const fde_status st = sync_scalars(c);
+  if (st != FDE_OK) return st;
+  for (int j = 0; j < count; ++j) out[j] = c->h_scal[fde::kD0 + j];
+  return FDE_OK;
+}
+
 fde_status adjoint_solve_impl(fde_ctx* c, const double* yhat, const double* y, const double* wy, double* lam) {
-  (void)c; (void)yhat; (void)y; (void)wy; (void)lam;
-  return (fde_status)fail(FDE_EINVAL, "fde_grad: adjoint_solve = 1 is not available in this build");
+  using namespace fde;
+  const int64_t plane = (int64_t)c->nx * c->ny;
+  SliceOps op{c, plane};
+  const double tol = 1e-13;
+  const int maxit = 500;
+  const double iht = 1.0 / c->su.ht;
+  double* f = c->bvec;
+  HIP_TRY(launch_adjoint_rhs(c->N, (int)plane, c->wts, y, yhat, wy, f, c->stream));
+  double *bk = c->By, *r = c->r, *rh = c->q, *p = c->pk, *v = c->fw, *sv = c->ar, *tv = c->Ru, *ph = c->av,
+         *sh = c->ac;
+  for (int k = c->nt - 1; k >= 0; --k) {
+    double* x = lam + (size_t)k * plane;
+    const double* fk = f + (size_t)k * plane;
+    const double* xn = (k + 1 < c->nt) ? lam + (size_t)(k + 1) * plane : nullptr;
+    // b_k = f_k + lambda_{k+1}/h_t ; x0 = lambda_{k+1}
+    HIP_TRY(launch_lincomb(plane, 1.0, fk, iht, xn, 0.0, nullptr, bk, c->stream));
+    HIP_TRY(launch_lincomb(plane, 1.0, xn, 0.0, nullptr, 0.0, nullptr, x, c->stream));
+    HIP_TRY(op.applyAT(x, v));
+    HIP_TRY(launch_lincomb(plane, 1.0, bk, -1.0, v, 0.0, nullptr, r, c->stream));
+    HIP_TRY(launch_lincomb(plane, 1.0, r, 0.0, nullptr, 0.0, nullptr, rh, c->stream));
+    HIP_TRY(launch_lincomb(plane, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, p, c->stream));
+    HIP_TRY(launch_lincomb(plane, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, v, c->stream));
+    double d[4];
+    {
+      const double* a2[2] = {bk, r};
+      const double* b2[2] = {bk, r};
+      HIP_TRY(op.dots(2, a2, b2));
+      fde_status st = read_dots(c, d, 2);
+      if (st != FDE_OK) return st;
+    }
+    const double bnorm = std::sqrt(d[0]);
+    double rr = d[1];
+    if (bnorm == 0.0 || std::sqrt(rr) <= tol * bnorm) continue;
+    double rho = 1.0, alpha = 1.0, omega = 1.0, rho1 = rr;  // (rhat, r) = (r, r) at the start
+    bool ok = false;
+    for (int it = 0; it < maxit; ++it) {
+      const double beta = (rho1 / rho) * (alpha / omega);
+      // p = r + beta (p - omega v)
+      HIP_TRY(launch_lincomb(plane, 1.0, r, beta, p, -beta * omega, v, p, c->stream));
+      HIP_TRY(op.precond(p, ph));
+      HIP_TRY(op.applyAT(ph, v));
+      {
+        const double* a1[1] = {rh};
+        const double* b1[1] = {v};
+        HIP_TRY(op.dots(1, a1, b1));
+        fde_status st = read_dots(c, d, 1);
+        if (st != FDE_OK) return st;
+      }
+      alpha = rho1 / d[0];
+      HIP_TRY(launch_lincomb(plane, 1.0, r, -alpha, v, 0.0, nullptr, sv, c->stream));
+      HIP_TRY(op.precond(sv, sh));
+      HIP_TRY(op.applyAT(sh, tv));
+      {
+        const double* a3[3] = {sv, tv, tv};
+        const double* b3[3] = {sv, sv, tv};
+        HIP_TRY(op.dots(3, a3, b3));
+        fde_status st = read_dots(c, d, 3);
+        if (st != FDE_OK) return st;
+      }
+      if (std::sqrt(d[0]) <= tol * bnorm) {
+        HIP_TRY(launch_lincomb(plane, 1.0, x, alpha, ph, 0.0, nullptr, x, c->stream));
+        ok = true;
+        break;
+      }
+      omega = d[1] / d[2];
+      HIP_TRY(launch_lincomb(plane, 1.0, x, alpha, ph, omega, sh, x, c->stream));
+      HIP_TRY(launch_lincomb(plane, 1.0, sv, -omega, tv, 0.0, nullptr, r, c->stream));
+      {
+        const double* a2[2] = {r, rh};
+        const double* b2[2] = {r, r};
+        HIP_TRY(op.dots(2, a2, b2));
+        fde_status st = read_dots(c, d, 2);
+        if (st != FDE_OK) return st;
+      }
+      if (!std::isfinite(d[0])) return (fde_status)fail(FDE_ENONFINITE, "non-finite residual in the adjoint solve");
+      if (std::sqrt(d[0]) <= tol * bnorm) {
+        ok = true;
+        break;
+      }
+      rho = rho1;
+      rho1 = d[1];
+    }
+    if (!ok) return (fde_status)fail(FDE_ENOTCONV, "adjoint solve: BiCGSTAB did not converge in a time step");
+  }
+  return FDE_OK;
 }
 
 fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void* stream, fde_ctx** out) {
@@ -459,6 +604,9 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   chk(c->alloc(&c->part_rr, (size_t)c->maxpart));
   chk(c->alloc(&c->part_rz, (size_t)c->maxpart));
   chk(c->alloc(&c->part_max, 3 * (size_t)c->maxpart));
+  chk(c->alloc(&c->part_dots, 4 * (size_t)2048));
+  chk(upload_c(c, &c->adj_lt, std::vector<cd>{cd(1.0 / s.ht, 0.0)}));
+  chk(upload_tw(c, &c->adj_twt, std::vector<cd>{cd(1.0, 0.0)}, c->fp32));
   chk(c->alloc(&c->scal, fde::kNumScalars));
   chk(c->alloc(&c->ints, fde::kNumInts));
   if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_scal, sizeof(double) * fde::kNumScalars, hipHostMallocDefault));
@@ -663,8 +811,8 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
     st.r_y = c->h_scal[fde::kResY];
     st.r_u = c->h_scal[fde::kResU];
     if (std::isnan(st.r_p) || std::isnan(st.r_y) || std::isnan(st.r_u)) {
-      status = (fde_status)fail(FDE_ENONFINITE, "non-finite ADMM residual");
-      break;
+      if (stats) *stats = st;
+      return (fde_status)fail(FDE_ENONFINITE, "non-finite ADMM residual");
     }
     prev_min = std::fmin(st.r_p, std::fmin(st.r_y, st.r_u));
     // 6. termination (Sec. 6.1)
@@ -672,6 +820,14 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
       status = FDE_OK;
       break;
     }
+  }
+  {
+    int nb = 0;
+    HIP_TRY(fde::launch_objective(c->N, c->nx * c->ny, c->wts, q.gamma, y, yhat, u, c->part_pq, c->stream, &nb));
+    HIP_TRY(fde::launch_pcg_scalar(fde::FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
+    const fde_status ss = sync_scalars(c);
+    if (ss != FDE_OK) return ss;
+    st.J = c->h_scal[fde::kDot];
   }
   st.t_total = now() - t0;
   st.t_pcg = t_pcg;

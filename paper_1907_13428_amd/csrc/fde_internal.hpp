@@ -66,6 +66,7 @@ struct PrecondArgs {
   const double2* lam_y;
   const double2* lam_t;
   double psi, a, inv_mbar, inv_n;  // s = a + |psi (lt - ly - lx)|^2 * inv_mbar; 1/(nx ny nt)
+  int div_mode;  // 0: divide by s (S~^{-1}); 1: multiply by 1/conj(psi (lt - ly - lx)) (C^{-T})
   // fused PCG pieces
   const double* q;        // x-forward: r -= alpha q (if non-null)
   double* xvec;           // x-forward: x += alpha p
@@ -98,6 +99,10 @@ enum ScalarSlot {
   kResY,
   kResU,
   kDot,       // scratch dot result
+  kD0,        // four slots written by launch_dots
+  kD1,
+  kD2,
+  kD3,
   kNumScalars
 };
 enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kNumInts };
@@ -139,6 +144,18 @@ hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi,
 hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
                               int* nblocks);
 hipError_t launch_max3_finalize(const double* partial, int nblocks, double* scal, hipStream_t s);
+// up to four dot products (a[j], b[j]) in one pass; sums land in scal[kD0 + j]
+hipError_t launch_dots(int64_t n, int count, const double* const* a, const double* const* b, double* partial,
+                       double* scal, hipStream_t s);
+// out = c0 x0 + c1 x1 + c2 x2 (null inputs skipped); out may alias an input
+hipError_t launch_lincomb(int64_t n, double c0, const double* x0, double c1, const double* x1, double c2,
+                          const double* x2, double* out, hipStream_t s);
+// f = -J1 (y - yhat) - wy
+hipError_t launch_adjoint_rhs(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
+                              const double* wy, double* f, hipStream_t s);
+// partial sums of 1/2 J1 (y - yhat)^2 + gamma/2 J1 u^2
+hipError_t launch_objective(int64_t n, int plane, const double* wts, double gamma, const double* y,
+                            const double* yhat, const double* u, double* partial, hipStream_t s, int* nb);
 // gradient pieces: dyhat = -J1 (y - yhat), lam = psi p
 hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
                               const double* p, double psi, double* dyhat, double* lam, hipStream_t s);

@@ -115,7 +115,9 @@ template <int L> struct CCfg {
   static_assert(P >= 1, "tile");
 };
 
-// MODE 0: y-direction, sign SIGN.  MODE 1: t-direction with the eigenvalue division.
+// MODE 0: y-direction, sign SIGN.  MODE 1: t-direction with the eigenvalue
+// division by s (S~^{-1}).  MODE 2: t-direction with the product by
+// 1 / conj(psi (lt - ly - lx)), the inverse of the transposed circulant.
 template <int L, typename TS, int MODE, int SIGN>
 __global__ __launch_bounds__(CCfg<L>::NT) void k_pre_cc(PrecondArgs a) {
   using V = cplx<TS>;
@@ -169,9 +171,16 @@ __global__ __launch_bounds__(CCfg<L>::NT) void k_pre_cc(PrecondArgs a) {
       const double2 lt = a.lam_t[kt];
       const double re = a.psi * (lt.x - ly.x - lx.x);
       const double im = a.psi * (lt.y - ly.y - lx.y);
-      const double s = a.a + (re * re + im * im) * a.inv_mbar;
-      const TS f = TS(a.inv_n / s);
-      v[e] = V{v[e].x * f, v[e].y * f};
+      if constexpr (MODE == 1) {
+        const double s = a.a + (re * re + im * im) * a.inv_mbar;
+        const TS f = TS(a.inv_n / s);
+        v[e] = V{v[e].x * f, v[e].y * f};
+      } else {
+        // 1 / conj(re + i im) = (re + i im) / (re^2 + im^2)
+        const double m = a.inv_n / (re * re + im * im);
+        const TS fr = TS(re * m), fi = TS(im * m);
+        v[e] = V{v[e].x * fr - v[e].y * fi, v[e].x * fi + v[e].y * fr};
+      }
     }
     line_fft<L, E, +1>(v, buf, t, tw);
   }
@@ -283,7 +292,8 @@ template <int L, typename TS>
 static hipError_t pre_t(const PrecondArgs& a, hipStream_t s) {
   using C = CCfg<L>;
   const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
-  k_pre_cc<L, TS, 1, -1><<<blocks, C::NT, 0, s>>>(a);
+  if (a.div_mode == 1) k_pre_cc<L, TS, 2, -1><<<blocks, C::NT, 0, s>>>(a);
+  else k_pre_cc<L, TS, 1, -1><<<blocks, C::NT, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -333,6 +343,7 @@ static hipError_t precond_T(const PrecondArgs& a, int stage, hipStream_t s, int*
   switch (a.nt) {
 #define CASE(Lv) case Lv: err = pre_t<Lv, TS>(a2, s); break;
     FDE_FOR_DIM_LENGTHS(CASE)
+    CASE(1)
 #undef CASE
     default: return hipErrorInvalidValue;
   }

@@ -258,6 +258,105 @@ __global__ __launch_bounds__(kBlock) void k_grad_fields(int64_t n, int plane, co
   }
 }
 
+struct DotArgs {
+  const double* a[4];
+  const double* b[4];
+};
+
+__global__ __launch_bounds__(kBlock) void k_dots(int64_t n, int count, DotArgs d, double* partial) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < count) s[j] += d.a[j][i] * d.b[j][i];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (j < count) {
+      const double r = block_sum<kBlock>(s[j]);
+      if (threadIdx.x == 0) partial[j * gridDim.x + blockIdx.x] = r;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dots_finalize(int count, int nb, const double* partial, double* scal) {
+  for (int j = 0; j < count; ++j) {
+    const double r = ordered_sum(partial + (size_t)j * nb, nb);
+    if (threadIdx.x == 0) scal[kD0 + j] = r;
+  }
+}
+
+hipError_t launch_dots(int64_t n, int count, const double* const* a, const double* const* b, double* partial,
+                       double* scal, hipStream_t s) {
+  DotArgs d{};
+  for (int j = 0; j < 4; ++j) {
+    d.a[j] = j < count ? a[j] : nullptr;
+    d.b[j] = j < count ? b[j] : nullptr;
+  }
+  const int blocks = vec_blocks(n);
+  k_dots<<<blocks, kBlock, 0, s>>>(n, count, d, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_dots_finalize<<<1, kBlock, 0, s>>>(count, blocks, partial, scal);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_lincomb(int64_t n, double c0, const double* x0, double c1,
+                                                    const double* x1, double c2, const double* x2, double* out) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    double v = 0.0;
+    if (x0) v += c0 * x0[i];
+    if (x1) v += c1 * x1[i];
+    if (x2) v += c2 * x2[i];
+    out[i] = v;
+  }
+}
+
+hipError_t launch_lincomb(int64_t n, double c0, const double* x0, double c1, const double* x1, double c2,
+                          const double* x2, double* out, hipStream_t s) {
+  k_lincomb<<<vec_blocks(n), kBlock, 0, s>>>(n, c0, x0, c1, x1, c2, x2, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_adjoint_rhs(int64_t n, int plane, const double* wts, const double* y,
+                                                        const double* yhat, const double* wy, double* f) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const int t = (int)(i / plane);
+    f[i] = -wts[t] * (y[i] - yhat[i]) - wy[i];
+  }
+}
+
+hipError_t launch_adjoint_rhs(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
+                              const double* wy, double* f, hipStream_t s) {
+  k_adjoint_rhs<<<vec_blocks(n), kBlock, 0, s>>>(n, plane, wts, y, yhat, wy, f);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_objective(int64_t n, int plane, const double* wts, double gamma,
+                                                      const double* y, const double* yhat, const double* u,
+                                                      double* partial) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const int t = (int)(i / plane);
+    const double e = y[i] - yhat[i];
+    s += 0.5 * wts[t] * (e * e + gamma * u[i] * u[i]);
+  }
+  const double r = block_sum<kBlock>(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+hipError_t launch_objective(int64_t n, int plane, const double* wts, double gamma, const double* y,
+                            const double* yhat, const double* u, double* partial, hipStream_t s, int* nb) {
+  const int blocks = vec_blocks(n);
+  if (nb) *nb = blocks;
+  k_objective<<<blocks, kBlock, 0, s>>>(n, plane, wts, gamma, y, yhat, u, partial);
+  return hipGetLastError();
+}
+
 hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
                               const double* p, double psi, double* dyhat, double* lam, hipStream_t s) {
   k_grad_fields<<<vec_blocks(n), kBlock, 0, s>>>(n, plane, wts, y, yhat, p, psi, dyhat, lam);

@@ -194,3 +194,17 @@ def test_trapezoidal_weights_and_rho_option():
     # u = (g - D y)/s amplifies the y error by |D| ~ h^-alpha; compare y tightly
     assert np.max(np.abs(r.y - pol["y"])) < 1e-5
     assert kkt.rel(r.u, pol["u"]) < 1e-4
+
+
+@pytest.mark.parametrize("kind", ["mixed", "state"])
+def test_reduced_polish_equals_full_kkt_polish(kind):
+    """The reduced active-set polish (y eliminated through a sparse LU of D)
+    solves the same KKT system as the full sparse saddle-point solve."""
+    w = (W.small_mixed if kind == "mixed" else W.small_state)(nx=8, ny=6, nt=4)
+    r = admm.admm_solve(w)
+    a = kkt.polish(w, r.zy, r.zu, method="full")
+    b = kkt.polish(w, r.zy, r.zu, method="reduced")
+    assert a["ok"] and b["ok"]
+    for k in ("y", "u", "lam", "mu_y", "mu_u"):
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-9 * max(1.0, np.max(np.abs(a[k]))), k
+    assert abs(a["J"] - b["J"]) <= 1e-12 * abs(a["J"])

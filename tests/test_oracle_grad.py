@@ -67,3 +67,10 @@ def test_gradient_wrt_orders_central_difference(base, which):
     assert np.array_equal(active_set(w, pp), active_set(w, pol))
     fd = (pp["J"] - pm["J"]) / (2 * h)
     assert abs(fd - g) < 1e-6 * max(abs(g), 1e-3), (fd, g)
+
+
+def test_adjoint_time_stepping_equals_sparse_lu(base):
+    w, r, pol = base
+    a = grad.adjoint_multiplier(w, pol["y"], pol["mu_y"], method="lu")
+    b = grad.adjoint_multiplier(w, pol["y"], pol["mu_y"], method="steps")
+    assert kkt.rel(b, a) < 1e-11

@@ -122,3 +122,14 @@ def test_psi_is_the_smallest_step_power():
     w = W.small()
     d = op.disc_from(w)
     assert op.psi_scale(d) == min(1 / 8, (1 / 17) ** 1.5, (1 / 17) ** 1.3)
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_time_stepping_solver_inverts_D(var):
+    w = tiny(var=var)
+    d = op.disc_from(w)
+    D = op.assemble_D(d)
+    S = op.DSolver(d)
+    f = W.random_field((w.N, 3), 4)
+    np.testing.assert_allclose(D @ S.solve(f), f, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(D.T @ S.solve(f, trans=True), f, rtol=1e-10, atol=1e-10)
