@@ -201,6 +201,32 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
  * Synchronises the stream. */
 fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes);
 
+/* Batched form: many independent problems of uneven sizes solved together.
+ * Each instance has its own context (tables, workspace, graph-captured PCG
+ * iteration) on its own stream (default priority); one host thread drives
+ * all of them as resumable state machines, polling a HIP event per instance
+ * and enqueueing its next phase as soon as the previous one has finished,
+ * so the instances' kernels overlap on the GPU and no instance waits for
+ * another's host synchronisation.  concurrent = 0 runs the same solves one
+ * after the other (the sequential reference).
+ * Arrays indexed by instance: yhat[i], g[i] (g may be NULL, or g[i] NULL),
+ * and the iterate fields y[i] .. wu[i] (device fields of instance i's size,
+ * read as the starting point, overwritten).  The caller makes the inputs
+ * ready before the call (e.g. synchronises the stream that produced them);
+ * the call synchronises every instance stream before returning.
+ * stats[i], status[i] (host, may be NULL) receive per-instance results; the
+ * return value is the first negative instance status, else FDE_ENOTCONV if
+ * any instance hit its iteration limit, else FDE_OK. */
+typedef struct fde_batch fde_batch;
+fde_status fde_batch_create(int count, const fde_problem* probs, const fde_admm_params* prms,
+                            fde_batch** out);
+fde_status fde_batch_destroy(fde_batch* b);
+fde_status fde_batch_solve(fde_batch* b, int concurrent, const double* const* yhat,
+                           const double* const* g, double* const* y, double* const* u,
+                           double* const* zy, double* const* zu, double* const* p,
+                           double* const* wy, double* const* wu, fde_admm_stats* stats,
+                           int32_t* status);
+
 /* Last error message of the calling thread ("" if none). */
 const char* fde_last_error(void);
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -73,6 +74,7 @@ struct fde_ctx {
   int* ints = nullptr;
   double* h_scal = nullptr;  // pinned
   int* h_ints = nullptr;
+  hipEvent_t ev = nullptr;   // marks completion of the last posted readback
   std::vector<void*> allocs;
 
   // one PCG iteration captured as a HIP graph (re-captured when the
@@ -227,12 +229,33 @@ fde_status check_ctx(fde_ctx* c) {
   return FDE_OK;
 }
 
-fde_status sync_scalars(fde_ctx* c) {
+// Device scalars -> pinned host copies, then an event; the host learns the
+// outcome of enqueued work without blocking the stream.
+fde_status post_readback(fde_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * fde::kNumScalars, hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(c->h_ints, c->ints, sizeof(int) * fde::kNumInts, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipEventRecord(c->ev, c->stream));
   return FDE_OK;
+}
+
+fde_status wait_readback(fde_ctx* c) {
+  HIP_TRY(hipEventSynchronize(c->ev));
+  return FDE_OK;
+}
+
+// 1: ready, 0: pending, <0: error
+int readback_ready(fde_ctx* c) {
+  const hipError_t e = hipEventQuery(c->ev);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return fail(FDE_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
+}
+
+fde_status sync_scalars(fde_ctx* c) {
+  fde_status st = post_readback(c);
+  if (st != FDE_OK) return st;
+  return wait_readback(c);
 }
 
 // One PCG iteration (13 launches): q = S p ; alpha ; x += alpha p, r -= alpha q,
@@ -296,54 +319,239 @@ fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
   return FDE_OK;
 }
 
-// PCG on S x = b (x: initial guess in, solution out).  Returns status; fills iters/relres.
-fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit, int* iters, double* relres,
-                  int predict) {
+// PCG on S x = b (x: initial guess in, solution out), in two phases so that
+// several contexts can be driven from one host thread:
+//   krylov_begin     enqueue r = b - S x, the convergence test, z = S~^{-1} r,
+//                    p = z and a first chunk of iterations; post a readback
+//   krylov_continue  after the readback: finished, or enqueue two more
+//                    iterations and post another readback
+struct KrylovRun {
+  double* x = nullptr;
+  int maxit = 0;
+  int enqueued = 0;
+  int iters = 0;
+  double relres = 0;
+  fde_status status = FDE_OK;
+};
+
+fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int maxit, int predict, KrylovRun* kr) {
   using namespace fde;
   const int* done = c->ints + kDone;
-  // tolerance and iteration limit into device scalars
   const double tol2 = tol * tol;
   int nbv = 0, nb1 = 0, nb5 = 0;
-  // r = b - S x ; (r, r), (b, b)
+  kr->x = x;
+  kr->maxit = maxit;
+  kr->enqueued = 0;
+  // r = b - S x ; (r, r), (b, b) ; tolerance and iteration limit into the device slots
   HIP_TRY(apply_S(c, x, c->q, nullptr, nullptr, nullptr));
   HIP_TRY(launch_axpy_dot(VEC_RESID, c->N, b, c->q, c->r, c->scal, c->part_pq, nullptr, c->stream, &nbv));
   HIP_TRY(launch_pcg_scalar(FIN_INIT, c->part_pq, nbv, c->scal, c->ints, c->stream, tol2, maxit));
   HIP_TRY(launch_axpy_dot(VEC_ZERO_IF_BB0, c->N, nullptr, nullptr, x, c->scal, nullptr, nullptr, c->stream,
                           nullptr));
   // z = S~^{-1} r ; p = z ; rz = (r, z)
-  {
-    PrecondArgs a = pre_args(c, c->r, c->z);
-    a.partial2 = c->part_rz;
-    a.done = done;
-    HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
-    HIP_TRY(launch_pcg_scalar(FIN_RZ0, c->part_rz, nb5, c->scal, c->ints, c->stream));
-    HIP_TRY(launch_axpy_dot(VEC_COPY, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr));
-  }
-  int enqueued = 0;
-  int chunk = predict > 1 ? predict : 2;
-  fde_status st = FDE_OK;
+  PrecondArgs a = pre_args(c, c->r, c->z);
+  a.partial2 = c->part_rz;
+  a.done = done;
+  HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
+  HIP_TRY(launch_pcg_scalar(FIN_RZ0, c->part_rz, nb5, c->scal, c->ints, c->stream));
+  HIP_TRY(launch_axpy_dot(VEC_COPY, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr));
   if (c->use_graph) {
-    st = ensure_pcg_graph(c, x);
+    const fde_status st = ensure_pcg_graph(c, x);
     if (st != FDE_OK) return st;
   }
-  while (true) {
-    for (int k = 0; k < chunk && enqueued < maxit; ++k, ++enqueued) {
-      if (c->use_graph) {
-        HIP_TRY(hipGraphLaunch(c->pcg_exec, c->stream));
-      } else {
-        HIP_TRY(enqueue_pcg_iteration(c, x));
+  const int chunk = predict > 1 ? predict : 2;
+  for (int k = 0; k < chunk && kr->enqueued < maxit; ++k, ++kr->enqueued) {
+    if (c->use_graph) HIP_TRY(hipGraphLaunch(c->pcg_exec, c->stream));
+    else HIP_TRY(enqueue_pcg_iteration(c, x));
+  }
+  return post_readback(c);
+}
+
+// returns 1 when finished (kr->status, iters, relres set), 0 when more work was enqueued
+int krylov_continue(fde_ctx* c, KrylovRun* kr) {
+  using namespace fde;
+  if (!(c->h_ints[kDone] || kr->enqueued >= kr->maxit)) {
+    for (int k = 0; k < 2 && kr->enqueued < kr->maxit; ++k, ++kr->enqueued) {
+      hipError_t e = c->use_graph ? hipGraphLaunch(c->pcg_exec, c->stream) : enqueue_pcg_iteration(c, kr->x);
+      if (e != hipSuccess) {
+        kr->status = (fde_status)fail(FDE_EHIP, std::string("PCG launch: ") + hipGetErrorString(e));
+        return 1;
       }
     }
-    if ((st = sync_scalars(c)) != FDE_OK) return st;
-    if (c->h_ints[kDone] || enqueued >= maxit) break;
-    chunk = 2;
+    const fde_status st = post_readback(c);
+    if (st != FDE_OK) {
+      kr->status = st;
+      return 1;
+    }
+    return 0;
   }
-  *iters = c->h_ints[kIter];
+  kr->iters = c->h_ints[kIter];
   const double bb = c->h_scal[kBB];
-  *relres = bb > 0 ? std::sqrt(c->h_scal[kRR] / bb) : 0.0;
-  if (c->h_ints[kConv] < 0) return (fde_status)fail(FDE_ENONFINITE, "non-finite residual in PCG");
-  if (c->h_ints[kConv] == 0) return FDE_ENOTCONV;
-  return FDE_OK;
+  kr->relres = bb > 0 ? std::sqrt(c->h_scal[kRR] / bb) : 0.0;
+  if (c->h_ints[kConv] < 0) kr->status = (fde_status)fail(FDE_ENONFINITE, "non-finite residual in PCG");
+  else if (c->h_ints[kConv] == 0) kr->status = FDE_ENOTCONV;
+  else kr->status = FDE_OK;
+  return 1;
+}
+
+fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit, int* iters, double* relres,
+                  int predict) {
+  KrylovRun kr;
+  fde_status st = krylov_begin(c, b, x, tol, maxit, predict, &kr);
+  if (st != FDE_OK) return st;
+  while (true) {
+    if ((st = wait_readback(c)) != FDE_OK) return st;
+    if (krylov_continue(c, &kr)) break;
+  }
+  *iters = kr.iters;
+  *relres = kr.relres;
+  return kr.status;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 as a resumable state machine.  admm_begin enqueues the first
+// iteration; each admm_advance call (made once the posted readback is
+// complete) consumes it and enqueues the next phase:
+//   PH_PCG  Krylov chunks of the x-step
+//   PH_RES  recovery, projection, dual update, residual maxima
+//   PH_OBJ  objective of the final iterate
+// ---------------------------------------------------------------------------
+enum AdmmPhase { PH_PCG = 0, PH_RES, PH_OBJ, PH_DONE };
+
+struct AdmmRun {
+  fde::AdmmConsts k{};
+  fde::AdmmFields f{};
+  int j = 0;
+  int phase = PH_DONE;
+  int predict = 0;
+  double prev_min = 0.0;
+  double t0 = 0, tp = 0, t_pcg = 0;
+  KrylovRun kr;
+  fde_admm_stats st{};
+  fde_status status = FDE_ENOTCONV;
+};
+
+fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
+  const auto& s = c->su;
+  const fde_admm_params& q = c->prm;
+  const double psi = s.psi, sti = psi / s.ht;
+  // 1. b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
+  HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
+  HIP_TRY(xpass(c, c->av, c->fb, true, sti, -psi, nullptr));
+  HIP_TRY(ypass(c, c->av, c->fb, c->bvec, true, -psi, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr, nullptr));
+  // 2. S y = b by PCG, warm-started from the previous y
+  const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(R->prev_min, 1e-4) : q.krylov_tol;
+  R->tp = now();
+  R->phase = PH_PCG;
+  return krylov_begin(c, c->bvec, R->f.y, tol, q.krylov_maxit, R->predict, &R->kr);
+}
+
+fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* g, double* y, double* u, double* zy,
+                      double* zu, double* p, double* wy, double* wu) {
+  const auto& s = c->su;
+  const fde_admm_params& q = c->prm;
+  *R = AdmmRun{};
+  R->t0 = now();
+  fde::AdmmConsts& k = R->k;
+  k.n = c->N;
+  k.plane = c->nx * c->ny;
+  k.nt = c->nt;
+  k.rho = q.rho;
+  k.delta = q.delta;
+  k.e_y = s.e_y;
+  k.e_u = s.e_u;
+  k.k_u = s.k_u;
+  k.ya = q.ya;
+  k.yb = q.yb;
+  k.ua = q.ua;
+  k.ub = q.ub;
+  k.wts = c->wts;
+  k.Mu = c->Mu;
+  k.Mp = c->Mp;
+  fde::AdmmFields& f = R->f;
+  f.yhat = yhat;
+  f.g = g;
+  f.y = y;
+  f.u = u;
+  f.zy = zy;
+  f.zu = zu;
+  f.p = p;
+  f.wy = wy;
+  f.wu = wu;
+  f.r = c->ar;
+  f.Ru = c->Ru;
+  f.v = c->av;
+  f.c = c->ac;
+  f.By = c->By;
+  f.partial = c->part_max;
+  R->j = 1;
+  return admm_enqueue_iteration(c, R);
+}
+
+// Consume the completed readback and enqueue the next phase.  A negative
+// return is an error (the run is over); R->phase == PH_DONE marks the end.
+fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
+  const auto& s = c->su;
+  const fde_admm_params& q = c->prm;
+  const double psi = s.psi, sti = psi / s.ht;
+  switch (R->phase) {
+    case PH_PCG: {
+      if (!krylov_continue(c, &R->kr)) return FDE_OK;
+      R->t_pcg += now() - R->tp;
+      if (R->kr.status < 0) {
+        R->phase = PH_DONE;
+        return R->kr.status;
+      }
+      const int it = R->kr.iters;
+      R->predict = it > 2 ? it - 1 : 2;
+      R->st.pcg_total += it;
+      R->st.pcg_last = it;
+      if (it > R->st.pcg_max) R->st.pcg_max = it;
+      // 3-5. By ; p, u recovery ; projection ; dual updates ; residual maxima
+      HIP_TRY(xpass(c, R->f.y, c->fa, false, sti, -psi, nullptr));
+      HIP_TRY(ypass(c, R->f.y, c->fa, c->By, false, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                    nullptr));
+      int nb = 0;
+      HIP_TRY(fde::launch_admm_update(R->k, R->f, psi, c->stream, &nb));
+      HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
+      R->phase = PH_RES;
+      return post_readback(c);
+    }
+    case PH_RES: {
+      fde_admm_stats& st = R->st;
+      st.admm_iters = R->j;
+      st.r_p = c->h_scal[fde::kResP];
+      st.r_y = c->h_scal[fde::kResY];
+      st.r_u = c->h_scal[fde::kResU];
+      if (std::isnan(st.r_p) || std::isnan(st.r_y) || std::isnan(st.r_u)) {
+        R->phase = PH_DONE;
+        return (fde_status)fail(FDE_ENONFINITE, "non-finite ADMM residual");
+      }
+      R->prev_min = std::fmin(st.r_p, std::fmin(st.r_y, st.r_u));
+      // 6. termination (Sec. 6.1)
+      const bool conv = q.admm_tol > 0 && std::fmax(st.r_p, std::fmax(st.r_y, st.r_u)) <= q.admm_tol;
+      if (conv) R->status = FDE_OK;
+      if (conv || R->j >= q.admm_maxit) {
+        int nb = 0;
+        HIP_TRY(fde::launch_objective(c->N, c->nx * c->ny, c->wts, q.gamma, R->f.y, R->f.yhat, R->f.u, c->part_pq,
+                                      c->stream, &nb));
+        HIP_TRY(fde::launch_pcg_scalar(fde::FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
+        R->phase = PH_OBJ;
+        return post_readback(c);
+      }
+      R->j += 1;
+      return admm_enqueue_iteration(c, R);
+    }
+    case PH_OBJ: {
+      R->st.J = c->h_scal[fde::kDot];
+      R->st.t_total = now() - R->t0;
+      R->st.t_pcg = R->t_pcg;
+      R->phase = PH_DONE;
+      return FDE_OK;
+    }
+    default:
+      return FDE_OK;
+  }
 }
 
 fde_status free_all(fde_ctx* c) {
@@ -352,6 +560,8 @@ fde_status free_all(fde_ctx* c) {
   c->cap_stream = nullptr;
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  c->ev = nullptr;
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
   c->h_scal = nullptr;
@@ -611,6 +821,7 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   chk(c->alloc(&c->ints, fde::kNumInts));
   if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_scal, sizeof(double) * fde::kNumScalars, hipHostMallocDefault));
   if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_ints, sizeof(int) * fde::kNumInts, hipHostMallocDefault));
+  if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
   if (e == hipSuccess) chk(hipMemset(c->scal, 0, sizeof(double) * fde::kNumScalars));
   if (e == hipSuccess) chk(hipMemset(c->ints, 0, sizeof(int) * fde::kNumInts));
   if (e != hipSuccess) {
@@ -737,102 +948,120 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!yhat || !y || !u || !zy || !zu || !p || !wy || !wu)
     return (fde_status)fail(FDE_EINVAL, "fde_admm_solve: null field");
-  fde_ctx* c = ctx;
-  const auto& s = c->su;
-  const fde_admm_params& q = c->prm;
-  const double t0 = now();
-  double t_pcg = 0.0;
-  fde::AdmmConsts k{};
-  k.n = c->N;
-  k.plane = c->nx * c->ny;
-  k.nt = c->nt;
-  k.rho = q.rho;
-  k.delta = q.delta;
-  k.e_y = s.e_y;
-  k.e_u = s.e_u;
-  k.k_u = s.k_u;
-  k.ya = q.ya;
-  k.yb = q.yb;
-  k.ua = q.ua;
-  k.ub = q.ub;
-  k.wts = c->wts;
-  k.Mu = c->Mu;
-  k.Mp = c->Mp;
-  fde::AdmmFields f{};
-  f.yhat = yhat;
-  f.g = g;
-  f.y = y;
-  f.u = u;
-  f.zy = zy;
-  f.zu = zu;
-  f.p = p;
-  f.wy = wy;
-  f.wu = wu;
-  f.r = c->ar;
-  f.Ru = c->Ru;
-  f.v = c->av;
-  f.c = c->ac;
-  f.By = c->By;
-  f.partial = c->part_max;
-  const double psi = s.psi, sti = psi / s.ht;
-  fde_admm_stats st{};
-  fde_status status = FDE_ENOTCONV;
-  double prev_min = 0.0;
-  int predict = 0;
-  for (int j = 1; j <= q.admm_maxit; ++j) {
-    // 1. right-hand side b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
-    HIP_TRY(fde::launch_admm_rhs(k, f, psi, c->stream));
-    HIP_TRY(xpass(c, c->av, c->fb, true, sti, -psi, nullptr));
-    HIP_TRY(ypass(c, c->av, c->fb, c->bvec, true, -psi, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr,
-                  nullptr));
-    // 2. S y = b by PCG, warm-started from the previous y
-    const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(prev_min, 1e-4) : q.krylov_tol;
-    int it = 0;
-    double rel = 0;
-    const double tp = now();
-    const fde_status ks = krylov(c, c->bvec, y, tol, q.krylov_maxit, &it, &rel, predict);
-    t_pcg += now() - tp;
-    if (ks < 0) return ks;
-    predict = it > 2 ? it - 1 : 2;
-    st.pcg_total += it;
-    st.pcg_last = it;
-    if (it > st.pcg_max) st.pcg_max = it;
-    // 3-5. By ; p, u recovery ; projection ; dual updates ; residual maxima
-    HIP_TRY(xpass(c, y, c->fa, false, sti, -psi, nullptr));
-    HIP_TRY(ypass(c, y, c->fa, c->By, false, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  nullptr));
-    int nb = 0;
-    HIP_TRY(fde::launch_admm_update(k, f, psi, c->stream, &nb));
-    HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
-    fde_status ss = sync_scalars(c);
-    if (ss != FDE_OK) return ss;
-    st.admm_iters = j;
-    st.r_p = c->h_scal[fde::kResP];
-    st.r_y = c->h_scal[fde::kResY];
-    st.r_u = c->h_scal[fde::kResU];
-    if (std::isnan(st.r_p) || std::isnan(st.r_y) || std::isnan(st.r_u)) {
-      if (stats) *stats = st;
-      return (fde_status)fail(FDE_ENONFINITE, "non-finite ADMM residual");
-    }
-    prev_min = std::fmin(st.r_p, std::fmin(st.r_y, st.r_u));
-    // 6. termination (Sec. 6.1)
-    if (q.admm_tol > 0 && std::fmax(st.r_p, std::fmax(st.r_y, st.r_u)) <= q.admm_tol) {
-      status = FDE_OK;
-      break;
-    }
+  AdmmRun R;
+  fde_status st = admm_begin(ctx, &R, yhat, g, y, u, zy, zu, p, wy, wu);
+  while (st >= 0 && R.phase != PH_DONE) {
+    if ((st = wait_readback(ctx)) != FDE_OK) break;
+    st = admm_advance(ctx, &R);
   }
-  {
-    int nb = 0;
-    HIP_TRY(fde::launch_objective(c->N, c->nx * c->ny, c->wts, q.gamma, y, yhat, u, c->part_pq, c->stream, &nb));
-    HIP_TRY(fde::launch_pcg_scalar(fde::FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
-    const fde_status ss = sync_scalars(c);
-    if (ss != FDE_OK) return ss;
-    st.J = c->h_scal[fde::kDot];
+  if (stats) *stats = R.st;
+  if (st < 0) return st;
+  return R.status;
+}
+
+}  // extern "C"
+
+struct fde_batch {
+  std::vector<fde_ctx*> ctx;
+  std::vector<hipStream_t> streams;
+};
+
+namespace {
+void batch_free(fde_batch* b) {
+  for (fde_ctx* c : b->ctx) fde_destroy(c);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+}
+}  // namespace
+
+extern "C" {
+
+fde_status fde_batch_create(int count, const fde_problem* probs, const fde_admm_params* prms, fde_batch** out) {
+  if (!out || !probs || !prms || count <= 0) return (fde_status)fail(FDE_EINVAL, "fde_batch_create: bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const fde_status v = fde_validate(&probs[i], &prms[i]);
+    if (v != FDE_OK) return (fde_status)fail(v, "instance " + std::to_string(i) + ": " + g_err);
   }
-  st.t_total = now() - t0;
-  st.t_pcg = t_pcg;
-  if (stats) *stats = st;
-  return status;
+  auto* b = new fde_batch();
+  for (int i = 0; i < count; ++i) {
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      batch_free(b);
+      return (fde_status)fail(FDE_EHIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    b->streams.push_back(s);
+    fde_ctx* c = nullptr;
+    const fde_status st = fde_create(&probs[i], &prms[i], s, &c);
+    if (st != FDE_OK) {
+      const std::string msg = g_err;
+      batch_free(b);
+      return (fde_status)fail(st, "instance " + std::to_string(i) + ": " + msg);
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return FDE_OK;
+}
+
+fde_status fde_batch_destroy(fde_batch* b) {
+  if (b) batch_free(b);
+  return FDE_OK;
+}
+
+fde_status fde_batch_solve(fde_batch* b, int concurrent, const double* const* yhat, const double* const* g,
+                           double* const* y, double* const* u, double* const* zy, double* const* zu, double* const* p,
+                           double* const* wy, double* const* wu, fde_admm_stats* stats, int32_t* status) {
+  if (!b || !yhat || !y || !u || !zy || !zu || !p || !wy || !wu)
+    return (fde_status)fail(FDE_EINVAL, "fde_batch_solve: null argument");
+  const int n = (int)b->ctx.size();
+  std::vector<fde_status> res(n, FDE_OK);
+  if (!concurrent) {
+    for (int i = 0; i < n; ++i) {
+      fde_admm_stats st{};
+      res[i] = fde_admm_solve(b->ctx[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i],
+                              &st);
+      if (stats) stats[i] = st;
+    }
+  } else {
+    std::vector<AdmmRun> R(n);
+    std::vector<char> live(n, 0);
+    int remaining = 0;
+    for (int i = 0; i < n; ++i) {
+      res[i] = admm_begin(b->ctx[i], &R[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i]);
+      if (res[i] >= 0) {
+        live[i] = 1;
+        ++remaining;
+      }
+    }
+    while (remaining > 0) {
+      bool progress = false;
+      for (int i = 0; i < n; ++i) {
+        if (!live[i]) continue;
+        const int r = readback_ready(b->ctx[i]);
+        if (r == 0) continue;
+        progress = true;
+        fde_status st = (r < 0) ? FDE_EHIP : admm_advance(b->ctx[i], &R[i]);
+        if (st < 0 || R[i].phase == PH_DONE) {
+          res[i] = st < 0 ? st : R[i].status;
+          live[i] = 0;
+          --remaining;
+        }
+      }
+      if (!progress) std::this_thread::yield();
+    }
+    for (int i = 0; i < n; ++i)
+      if (stats) stats[i] = R[i].st;
+  }
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  fde_status worst = FDE_OK;
+  for (int i = 0; i < n; ++i) {
+    if (status) status[i] = res[i];
+    if (res[i] < 0 && worst >= 0) worst = res[i];
+    if (res[i] == FDE_ENOTCONV && worst == FDE_OK) worst = FDE_ENOTCONV;
+  }
+  return worst;
 }
 
 fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const double* p, const double* wy,

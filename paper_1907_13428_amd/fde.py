@@ -23,7 +23,7 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
             "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_time_pass",
-            "fde_last_error", "fde_version"]
+            "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error", "fde_version"]
 
 PASS_NAMES = ["xpass_B", "ypass_B", "xpass_BT", "ypass_BT", "pre_xfwd", "pre_yfwd", "pre_t_div", "pre_yinv",
               "pre_xinv"]
@@ -84,6 +84,12 @@ def lib():
         L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
         L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        L.fde_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(Params),
+                                       ctypes.POINTER(P)]
+        L.fde_batch_destroy.argtypes = [P]
+        L.fde_batch_solve.argtypes = [P, ctypes.c_int, PP, PP, PP, PP, PP, PP, PP, PP, PP, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(ctypes.c_int32)]
         L.fde_last_error.restype = ctypes.c_char_p
         L.fde_version.restype = ctypes.c_char_p
         for name in EXPORTED:
@@ -252,3 +258,59 @@ class Context:
         _check(lib().fde_grad(self._h, _dptr(yhat), _dptr(y), _dptr(p), _dptr(wy), int(adjoint_solve),
                               _dptr(dyhat), dab, _dptr(lam)), False)
         return dyhat, dab[0], dab[1]
+
+
+class Batch:
+    """Many independent instances (uneven sizes) solved together: one context
+    and stream per instance, driven concurrently by the library."""
+
+    FIELDS = ("y", "u", "zy", "zu", "p", "wy", "wu")
+
+    def __init__(self, probs, prms):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("a GPU is required (libfde.so runs on gfx950)")
+        n = len(probs)
+        self.count = n
+        self.shapes = [(p.nt, p.ny, p.nx) for p in probs]
+        self._probs = (Problem * n)(*probs)
+        self._prms = (Params * n)(*prms)
+        self._keep = [getattr(p, "_keep", None) for p in probs]
+        h = ctypes.c_void_p()
+        _check(lib().fde_batch_create(n, self._probs, self._prms, ctypes.byref(h)), allow_notconv=False)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().fde_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def solve(self, yhats, states=None, concurrent=True):
+        """Solve every instance; returns (states, list of stats dicts, list of statuses)."""
+        import torch
+
+        n = self.count
+        if states is None:
+            states = [{k: torch.zeros(self.shapes[i], dtype=torch.float64, device="cuda") for k in self.FIELDS}
+                      for i in range(n)]
+        torch.cuda.synchronize()
+        arr = lambda ts: (ctypes.c_void_p * n)(*[_dptr(t).value for t in ts])
+        yh = arr(yhats)
+        cols = [arr([states[i][k] for i in range(n)]) for k in self.FIELDS]
+        st = (Stats * n)()
+        code = (ctypes.c_int32 * n)()
+        _check(lib().fde_batch_solve(self._h, int(bool(concurrent)), yh, None, *cols, st, code))
+        return states, [s.as_dict() for s in st], list(code)

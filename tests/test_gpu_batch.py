@@ -1,0 +1,69 @@
+"""GPU: the batched form (uneven instances driven concurrently)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import admm
+from tests.gpu_util import banner, dev, host, rel
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1907_13428_amd import fde  # noqa: E402
+
+
+def uneven(count=6, seed=5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        nx, ny = int(rng.choice([8, 12, 16, 24])), int(rng.choice([8, 12, 16]))
+        nt = int(rng.choice([4, 6, 8]))
+        w = W.small_mixed(nx=nx, ny=ny, nt=nt).replace(alpha=float(rng.uniform(1.1, 1.9)),
+                                                       beta=float(rng.uniform(1.1, 1.9)),
+                                                       gamma=float(10 ** rng.uniform(-5, -3)))
+        w.yhat = W.target_grf(nx, ny, nt, W.BASE_SEED + 100 + i)
+        out.append(w)
+    return out
+
+
+def run(ws, concurrent, fp32=0):
+    probs, prms = zip(*[fde.from_workload(w, precond_fp32=fp32) for w in ws])
+    with fde.Batch(list(probs), list(prms)) as b:
+        states, stats, codes = b.solve([dev(w.yhat) for w in ws], concurrent=concurrent)
+        return [{k: host(v) for k, v in s.items()} for s in states], stats, codes
+
+
+def test_batch_concurrent_equals_sequential_and_oracle():
+    banner("batch concurrent vs sequential")
+    ws = uneven()
+    a, sa, ca = run(ws, True)
+    b, sb, cb = run(ws, False)
+    assert ca == cb
+    for i in range(len(ws)):
+        assert sa[i]["admm_iters"] == sb[i]["admm_iters"]
+        for k in a[i]:
+            assert np.array_equal(a[i][k], b[i][k]), (i, k)
+    for i in (0, 3):
+        w = ws[i]
+        K = sa[i]["admm_iters"]
+        ref = admm.admm_solve(w, iters=K)
+        assert rel(a[i]["y"], ref.y) <= 1e-7 and rel(a[i]["u"], ref.u) <= 1e-7
+
+
+def test_batch_fp32_preconditioner_error_stated():
+    banner("batch fp32 precond")
+    ws = uneven(count=3, seed=8)
+    a, sa, _ = run(ws, True, fp32=1)
+    for i, w in enumerate(ws):
+        ref = admm.admm_solve(w, iters=sa[i]["admm_iters"])
+        assert rel(a[i]["y"], ref.y) <= 1e-7, i
+
+
+def test_batch_rejects_invalid_instance():
+    banner("batch invalid")
+    ws = uneven(count=2)
+    probs, prms = zip(*[fde.from_workload(w) for w in ws])
+    probs = list(probs)
+    probs[1].nx = 10
+    with pytest.raises(fde.FdeError) as e:
+        fde.Batch(probs, list(prms))
+    assert "instance 1" in str(e.value)
