@@ -14,7 +14,9 @@ iteration cap --full-cap) is timed as well, FP64 and with the FP32
 preconditioner; at this grid and delta = rho = 1 the ADMM residual on the
 control copy falls slowly, so the cap is normally reached and the record says
 so ("converged": false, residuals).  Each PCG pass is timed with HIP events
-for the roofline figure of the dominant kernel.  The
+for the roofline figure of the dominant kernel.  The batched leg runs 64
+uneven instances for a fixed ADMM budget each, concurrently with the FP32
+preconditioner and sequentially in FP64 ("solves" = budgeted runs).  The
 CPU oracle's PCG iteration on the same grid is timed on a bounded sample.
 Prints one JSON line.
 """
@@ -38,9 +40,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-full", action="store_true", help="skip the full cold-start solves")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=48)
     ap.add_argument("--full-cap", type=int, default=1500,
                     help="ADMM iteration cap of the cold-start solves (tolerance 1e-6)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--batch-cap", type=int, default=30, help="ADMM iterations per batched instance")
     return ap.parse_args()
 
 
@@ -72,6 +76,30 @@ def cpu_baseline(w, iters):
                       f"(S apply + no-FFT preconditioner), {dt:.1f} s"}
 
 
+def batched_leg(fde, torch, cap):
+    """64 uneven instances (sizes 64..512, nt 16/32, random orders and gamma, GRF
+    targets), each run for `cap` ADMM iterations: concurrently with the FP32
+    preconditioner (one stream and graph per instance, autotuned tiles) and
+    sequentially in FP64."""
+    import workloads as W
+
+    ws = W.batched()
+    yh = [torch.from_numpy(w.yhat).to("cuda") for w in ws]
+    rec = {"instances": len(ws), "points": sum(w.N for w in ws), "admm_iters_per_instance": cap}
+    for tag, fp32, conc in (("concurrent_fp32_precond", 1, True), ("sequential_fp64", 0, False)):
+        probs, prms = zip(*[fde.from_workload(w, precond_fp32=fp32, admm_maxit=cap) for w in ws])
+        with fde.Batch(list(probs), list(prms)) as b:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, stats, _ = b.solve(yh, concurrent=conc)
+            dt = time.perf_counter() - t0
+        pcg = sum(s["pcg_total"] for s in stats)
+        rec[tag] = {"s": round(dt, 3), "solves_per_s": round(len(ws) / dt, 2), "pcg_iters_per_s": round(pcg / dt, 1),
+                    "pcg_total": pcg}
+    rec["speedup"] = round(rec["sequential_fp64"]["s"] / rec["concurrent_fp32_precond"]["s"], 3)
+    return rec
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -94,6 +122,7 @@ def main():
     # ---- timed ADMM iterations (FP64) -------------------------------------
     prob, prm = fde.from_workload(w, admm_tol=0.0, admm_maxit=max(a.warmup, 1))
     ctx = fde.Context(prob, prm)
+    out["autotune"] = ctx.autotune()
     progress(f"warmup {a.warmup} ADMM iterations")
     state, st_w, _ = ctx.admm_solve(yhat)
     ctx.set_params(fde.from_workload(w, admm_tol=0.0, admm_maxit=a.steps)[1])
@@ -146,6 +175,11 @@ def main():
                     rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))
                 out[tag] = rec
         out["admm_solve_s"] = out["fp64"]["admm_solve_s"]
+
+    # ---- batched form: 64 uneven instances, concurrent vs sequential ---------
+    if not a.no_batch:
+        progress("batched instances")
+        out["batched"] = batched_leg(fde, torch, a.batch_cap)
 
     out["config"] = {"workload": "headline_256x256x64", "nx": 256, "ny": 256, "nt": 64, "alpha": 1.3, "beta": 1.7,
                      "gamma": 1e-6, "delta": 1.0, "rho": 1.0, "krylov_tol": 1e-10, "admm_tol": 1e-6,

@@ -123,7 +123,9 @@ fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, 
  * T. Chan eigen tables and twiddles on the host (FP64), copies them to the
  * device and allocates the workspace.  *out receives the context.  The PCG
  * iteration is replayed from a HIP graph captured on a private stream
- * (environment FDE_NO_GRAPH=1 at create time: plain kernel launches). */
+ * (environment FDE_NO_GRAPH=1 at create time: plain kernel launches).  The
+ * column tiles start at the widest variant (FDE_TILES=a,b,c at create time
+ * fixes the three variants; see fde_autotune). */
 fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream,
                       fde_ctx** out);
 fde_status fde_destroy(fde_ctx* ctx);
@@ -201,9 +203,22 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
  * Synchronises the stream. */
 fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes);
 
+/* Autotuner of the FFT column tiles: times the widest, half and quarter
+ * column-tile variants of the y-direction Toeplitz passes, the y-direction
+ * preconditioner passes and the t-direction pass on this context's grid
+ * (HIP events, workspace overwritten) and keeps the fastest.  Choices are
+ * cached per (nx, ny, nt, coefficient kind, precision) for the process and,
+ * when the environment names a file in FDE_TUNE_DB, appended to / read from
+ * it.  choices (host, 3 ints, may be NULL): column pairs per block of the
+ * y-pass, and the variant indices of the two preconditioner passes.  The
+ * results of every variant are identical up to the order of the partial
+ * sums of the fused dot products.  Synchronises the stream. */
+fde_status fde_autotune(fde_ctx* ctx, int32_t* choices);
+
 /* Batched form: many independent problems of uneven sizes solved together.
  * Each instance has its own context (tables, workspace, graph-captured PCG
- * iteration) on its own stream (default priority); one host thread drives
+ * iteration, tiles chosen by fde_autotune) on its own stream (default
+ * priority); one host thread drives
  * all of them as resumable state machines, polling a HIP event per instance
  * and enqueueing its next phase as soon as the previous one has finished,
  * so the instances' kernels overlap on the GPU and no instance waits for

@@ -8,11 +8,17 @@
 // and reads the flag back once per chunk.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <chrono>
 #include <thread>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -84,6 +90,8 @@ struct fde_ctx {
   hipGraphExec_t pcg_exec = nullptr;
   const double* pcg_graph_x = nullptr;
   bool use_graph = true;
+  // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
+  int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
 
   template <typename T>
   hipError_t alloc(T** p, size_t count) {
@@ -179,6 +187,7 @@ hipError_t ypass(fde_ctx* c, const double* in, const double* acc, double* out, b
   a.lamA = tr ? c->lyTA : c->lyA;
   a.lamB = tr ? c->lyTB : c->lyB;
   a.s_sp = s_sp;
+  a.tile = c->tile_line_y;
   a.acc = acc;
   a.oscale = osc;
   a.extra = extra;
@@ -221,6 +230,8 @@ fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
   a.inv_mbar = c->su.inv_mbar;
   a.inv_n = 1.0 / (double)c->N;
   a.scal = c->scal;
+  a.tile_y = c->tile_pre_y;
+  a.tile_t = c->tile_pre_t;
   return a;
 }
 
@@ -615,6 +626,7 @@ struct SliceOps {
     b.lamA = c->lyTA;
     b.lamB = c->lyTB;
     b.s_sp = -1.0;
+    b.tile = c->tile_line_y;
     return fde::launch_ypass(b, true, c->var, c->stream, nullptr);
   }
   // z = C(A)^{-T} r on one slice
@@ -753,6 +765,16 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   // FDE_NO_GRAPH=1 launches the PCG iteration kernel by kernel (no HIP graph)
   const char* ng = std::getenv("FDE_NO_GRAPH");
   c->use_graph = !(ng && ng[0] == '1');
+  // FDE_TILES=a,b,c fixes the column-tile variants (0..2) instead of the default widest tiles
+  if (const char* tv = std::getenv("FDE_TILES")) {
+    int a = 0, b = 0, d = 0;
+    if (std::sscanf(tv, "%d,%d,%d", &a, &b, &d) == 3) {
+      auto clampv = [](int v) { return v < 0 ? 0 : (v > 2 ? 2 : v); };
+      c->tile_line_y = clampv(a);
+      c->tile_pre_y = clampv(b);
+      c->tile_pre_t = clampv(d);
+    }
+  }
   auto& s = c->su;
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) {
@@ -1000,6 +1022,12 @@ fde_status fde_batch_create(int count, const fde_problem* probs, const fde_admm_
       return (fde_status)fail(st, "instance " + std::to_string(i) + ": " + msg);
     }
     b->ctx.push_back(c);
+    const fde_status ts = fde_autotune(c, nullptr);  // cached per shape
+    if (ts != FDE_OK) {
+      const std::string msg = g_err;
+      batch_free(b);
+      return (fde_status)fail(ts, "instance " + std::to_string(i) + " autotune: " + msg);
+    }
   }
   *out = b;
   return FDE_OK;
@@ -1096,6 +1124,7 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   b.lamA = c->dyA;
   b.lamB = c->dyB;
   b.s_sp = 1.0;
+  b.tile = c->tile_line_y;
   HIP_TRY(launch_ypass(b, false, c->var, c->stream, nullptr));
   double out[2];
   const double* fld[2] = {c->fa, c->fb};
@@ -1109,6 +1138,124 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   }
   dab[0] = out[0];
   dab[1] = out[1];
+  return FDE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// process-wide cache of tuned tile variants, keyed by the shape of the problem
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 3>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(fde_ctx* c) {
+  std::ostringstream k;
+  k << "nx=" << c->nx << ",ny=" << c->ny << ",nt=" << c->nt << ",var=" << (int)c->var << ",fp32=" << (int)c->fp32;
+  return k.str();
+}
+
+void tune_db_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("FDE_TUNE_DB");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string key;
+  std::array<int, 3> v{};
+  while (f >> key >> v[0] >> v[1] >> v[2]) g_tune[key] = v;
+}
+
+void tune_db_append(const std::string& key, const std::array<int, 3>& v) {
+  const char* path = std::getenv("FDE_TUNE_DB");
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << v[0] << " " << v[1] << " " << v[2] << "\n";
+}
+
+// mean microseconds of `reps` back-to-back launches between two events
+template <typename F>
+hipError_t time_launches(fde_ctx* c, int reps, F&& launch, double* us) {
+  hipError_t e = launch();
+  if (e != hipSuccess) return e;
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+  (void)hipEventRecord(e0, c->stream);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch();
+  (void)hipEventRecord(e1, c->stream);
+  (void)hipEventSynchronize(e1);
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *us = 1000.0 * ms / reps;
+  return e;
+}
+}  // namespace
+
+extern "C" {
+
+fde_status fde_autotune(fde_ctx* ctx, int32_t* choices) {
+  using namespace fde;
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  fde_ctx* c = ctx;
+  const std::string key = tune_key(c);
+  std::array<int, 3> best{0, 0, 0};
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_db_load();
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      best = it->second;
+      cached = true;
+    }
+  }
+  if (!cached) {
+    const size_t N = (size_t)c->N;
+    double* fields[] = {c->fa, c->fw, c->fb, c->q, c->pk};
+    for (double* f : fields) HIP_TRY(hipMemsetAsync(f, 0, N * sizeof(double), c->stream));
+    const size_t sb = (size_t)c->H * c->ny * c->nt * (c->fp32 ? 8 : 16);
+    HIP_TRY(hipMemsetAsync(c->spec, 0, sb, c->stream));
+    const double psi = c->su.psi;
+    const int reps = 10;
+    double t_best[3] = {1e30, 1e30, 1e30};
+    for (int v = 0; v < 3; ++v) {
+      double us = 0;
+      // the two y-passes of the S apply
+      c->tile_line_y = v;
+      HIP_TRY(time_launches(c, reps, [&]() -> hipError_t {
+        hipError_t e = ypass(c, c->pk, c->fa, c->fw, false, -psi, c->invMp, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr);
+        if (e != hipSuccess) return e;
+        return ypass(c, c->fw, c->fb, c->q, true, -psi, nullptr, c->pk, c->My, c->pk, c->part_pq, nullptr, nullptr);
+      }, &us));
+      if (us < t_best[0]) { t_best[0] = us; best[0] = v; }
+      // preconditioner y and t passes
+      c->tile_pre_y = v;
+      c->tile_pre_t = v;
+      PrecondArgs a = pre_args(c, c->r, c->z);
+      HIP_TRY(time_launches(c, reps, [&]() { return launch_precond_stage(a, c->fp32, 12, c->stream, nullptr, nullptr); },
+                            &us));
+      if (us < t_best[1]) { t_best[1] = us; best[1] = v; }
+      HIP_TRY(time_launches(c, reps, [&]() { return launch_precond_stage(a, c->fp32, 13, c->stream, nullptr, nullptr); },
+                            &us));
+      if (us < t_best[2]) { t_best[2] = us; best[2] = v; }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    tune_db_append(key, best);
+  }
+  c->tile_line_y = best[0];
+  c->tile_pre_y = best[1];
+  c->tile_pre_t = best[2];
+  drop_pcg_graph(c);  // the captured iteration used the previous tiles
+  if (choices) {
+    choices[0] = ypass_tile_width(2 * c->ny, best[0]);
+    choices[1] = best[1];
+    choices[2] = best[2];
+  }
   return FDE_OK;
 }
 

@@ -44,12 +44,14 @@ struct LinePassArgs {
   const double* dotv;    // may be nullptr: then no partial sums
   double* partial;       // one slot per block
   const int* done;       // early-exit flag (may be nullptr)
+  int tile;              // y-pass tile variant (autotuned): 0 widest, 1 half, 2 quarter
 };
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_xpass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
 hipError_t launch_ypass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
 bool fft_length_supported(int L);
+int ypass_tile_width(int L, int variant);  // column pairs per block of a variant (0 if unsupported)
 
 // ---------------------------------------------------------------------------
 // preconditioner passes: z = S~^{-1} r via a 3-D real FFT
@@ -67,6 +69,7 @@ struct PrecondArgs {
   const double2* lam_t;
   double psi, a, inv_mbar, inv_n;  // s = a + |psi (lt - ly - lx)|^2 * inv_mbar; 1/(nx ny nt)
   int div_mode;  // 0: divide by s (S~^{-1}); 1: multiply by 1/conj(psi (lt - ly - lx)) (C^{-T})
+  int tile_y, tile_t;  // column-tile variants of the y and t passes (autotuned)
   // fused PCG pieces
   const double* q;        // x-forward: r -= alpha q (if non-null)
   double* xvec;           // x-forward: x += alpha p

@@ -104,24 +104,26 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
 // passes 2/4 (y) and 3 (t): complex lines across rows of a [rows][H] plane,
 // P columns per block staged through LDS
 // ---------------------------------------------------------------------------
-template <int L> struct CCfg {
+// Tile variant S (chosen by the autotuner): P = Pmax >> S complex columns per block.
+template <int L, int S = 0> struct CCfg {
   static constexpr int E = default_E(L);
   static constexpr int T = L / E;
   static constexpr int cap(int a, int b) { return a < b ? a : b; }
-  // complex columns per block: at most 16, at most 256 threads, LDS tile within 128 KiB (FP64)
-  static constexpr int P = cap(cap(16, kPreThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  // widest tile: at most 16 columns, at most 256 threads, LDS tile within 128 KiB (FP64)
+  static constexpr int Pmax = cap(cap(16, kPreThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  static constexpr int P = (Pmax >> S) > 0 ? (Pmax >> S) : 1;
   static constexpr int NT = ((P * T + 63) / 64) * 64;
   static constexpr int RS = P + 1;
-  static_assert(P >= 1, "tile");
+  static_assert(Pmax >= 1, "tile");
 };
 
 // MODE 0: y-direction, sign SIGN.  MODE 1: t-direction with the eigenvalue
 // division by s (S~^{-1}).  MODE 2: t-direction with the product by
 // 1 / conj(psi (lt - ly - lx)), the inverse of the transposed circulant.
-template <int L, typename TS, int MODE, int SIGN>
-__global__ __launch_bounds__(CCfg<L>::NT) void k_pre_cc(PrecondArgs a) {
+template <int L, typename TS, int MODE, int SIGN, int S>
+__global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   using V = cplx<TS>;
-  using C = CCfg<L>;
+  using C = CCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   __shared__ V lds[lpad_size(L) * RS];
   if (a.done && *a.done) return;
@@ -279,22 +281,40 @@ static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) 
   return hipGetLastError();
 }
 
+template <int L, typename TS, int S>
+static hipError_t pre_y_S(const PrecondArgs& a, int sign, hipStream_t s) {
+  using C = CCfg<L, S>;
+  const int blocks = ((a.H + C::P - 1) / C::P) * a.nt;
+  if (sign < 0) k_pre_cc<L, TS, 0, -1, S><<<blocks, C::NT, 0, s>>>(a);
+  else k_pre_cc<L, TS, 0, +1, S><<<blocks, C::NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 template <int L, typename TS>
 static hipError_t pre_y(const PrecondArgs& a, int sign, hipStream_t s) {
-  using C = CCfg<L>;
-  const int blocks = ((a.H + C::P - 1) / C::P) * a.nt;
-  if (sign < 0) k_pre_cc<L, TS, 0, -1><<<blocks, C::NT, 0, s>>>(a);
-  else k_pre_cc<L, TS, 0, +1><<<blocks, C::NT, 0, s>>>(a);
+  switch (a.tile_y) {
+    case 1: return pre_y_S<L, TS, 1>(a, sign, s);
+    case 2: return pre_y_S<L, TS, 2>(a, sign, s);
+    default: return pre_y_S<L, TS, 0>(a, sign, s);
+  }
+}
+
+template <int L, typename TS, int S>
+static hipError_t pre_t_S(const PrecondArgs& a, hipStream_t s) {
+  using C = CCfg<L, S>;
+  const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
+  if (a.div_mode == 1) k_pre_cc<L, TS, 2, -1, S><<<blocks, C::NT, 0, s>>>(a);
+  else k_pre_cc<L, TS, 1, -1, S><<<blocks, C::NT, 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <int L, typename TS>
 static hipError_t pre_t(const PrecondArgs& a, hipStream_t s) {
-  using C = CCfg<L>;
-  const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
-  if (a.div_mode == 1) k_pre_cc<L, TS, 2, -1><<<blocks, C::NT, 0, s>>>(a);
-  else k_pre_cc<L, TS, 1, -1><<<blocks, C::NT, 0, s>>>(a);
-  return hipGetLastError();
+  switch (a.tile_t) {
+    case 1: return pre_t_S<L, TS, 1>(a, s);
+    case 2: return pre_t_S<L, TS, 2>(a, s);
+    default: return pre_t_S<L, TS, 0>(a, s);
+  }
 }
 
 template <typename TS>

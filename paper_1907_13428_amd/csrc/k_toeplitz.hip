@@ -120,20 +120,22 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
 // y-pass: a block owns one time slice and 2P adjacent x-columns; the tile is
 // staged through LDS so that every global access is row-contiguous
 // ---------------------------------------------------------------------------
-template <int L> struct YCfg {
+// Tile variant S (chosen by the autotuner): P = Pmax >> S column pairs per block.
+template <int L, int S = 0> struct YCfg {
   static constexpr int E = default_E(L);
   static constexpr int T = L / E;
   static constexpr int cap(int a, int b) { return a < b ? a : b; }
-  // column pairs per block: at most 8, at most 256 threads, LDS tile within 128 KiB
-  static constexpr int P = cap(cap(8, kLineThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  // widest tile: at most 8 column pairs, at most 256 threads, LDS tile within 128 KiB
+  static constexpr int Pmax = cap(cap(8, kLineThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  static constexpr int P = (Pmax >> S) > 0 ? (Pmax >> S) : 1;
   static constexpr int NT = ((P * T + 63) / 64) * 64;  // threads per block
   static constexpr int RS = P + 1;                     // LDS row stride (spare column P)
-  static_assert(P >= 1, "tile");
+  static_assert(Pmax >= 1, "tile");
 };
 
-template <int L, bool VAR, bool TRANS>
-__global__ __launch_bounds__(YCfg<L>::NT) void k_ypass(LinePassArgs a) {
-  using C = YCfg<L>;
+template <int L, bool VAR, bool TRANS, int S>
+__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
+  using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   constexpr int n = L / 2;
   constexpr int TX = 2 * P;
@@ -276,20 +278,39 @@ static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t 
   return hipGetLastError();
 }
 
-template <int L>
-static hipError_t ypass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
-  using C = YCfg<L>;
+template <int L, int S>
+static hipError_t ypass_LS(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  using C = YCfg<L, S>;
   const int tiles = (a.nx + 2 * C::P - 1) / (2 * C::P);
   const int blocks = tiles * a.nt;
   if (nb) *nb = blocks;
   if (var) {
-    if (tr) k_ypass<L, true, true><<<blocks, C::NT, 0, s>>>(a);
-    else k_ypass<L, true, false><<<blocks, C::NT, 0, s>>>(a);
+    if (tr) k_ypass<L, true, true, S><<<blocks, C::NT, 0, s>>>(a);
+    else k_ypass<L, true, false, S><<<blocks, C::NT, 0, s>>>(a);
   } else {
-    if (tr) k_ypass<L, false, true><<<blocks, C::NT, 0, s>>>(a);
-    else k_ypass<L, false, false><<<blocks, C::NT, 0, s>>>(a);
+    if (tr) k_ypass<L, false, true, S><<<blocks, C::NT, 0, s>>>(a);
+    else k_ypass<L, false, false, S><<<blocks, C::NT, 0, s>>>(a);
   }
   return hipGetLastError();
+}
+
+template <int L>
+static hipError_t ypass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
+  switch (a.tile) {
+    case 1: return ypass_LS<L, 1>(a, tr, var, s, nb);
+    case 2: return ypass_LS<L, 2>(a, tr, var, s, nb);
+    default: return ypass_LS<L, 0>(a, tr, var, s, nb);
+  }
+}
+
+int ypass_tile_width(int L, int variant) {
+  switch (L) {
+#define CASE(Lv) \
+  case Lv: return variant == 1 ? YCfg<Lv, 1>::P : variant == 2 ? YCfg<Lv, 2>::P : YCfg<Lv, 0>::P;
+    FDE_FOR_EMBED_LENGTHS(CASE)
+#undef CASE
+    default: return 0;
+  }
 }
 
 hipError_t launch_xpass(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {

@@ -23,7 +23,8 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
             "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_time_pass",
-            "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error", "fde_version"]
+            "fde_autotune", "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error",
+            "fde_version"]
 
 PASS_NAMES = ["xpass_B", "ypass_B", "xpass_BT", "ypass_BT", "pre_xfwd", "pre_yfwd", "pre_t_div", "pre_yinv",
               "pre_xinv"]
@@ -84,6 +85,7 @@ def lib():
         L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
         L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
+        L.fde_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
         PP = ctypes.POINTER(ctypes.c_void_p)
         L.fde_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                        ctypes.POINTER(P)]
@@ -244,6 +246,12 @@ class Context:
         status = _check(lib().fde_admm_solve(self._h, _dptr(yhat, "yhat"), _dptr(g, "g"), *args,
                                              ctypes.byref(st)))
         return state, st.as_dict(), status
+
+    def autotune(self):
+        """Pick the fastest column-tile variants for this grid; returns the choices."""
+        ch = (ctypes.c_int32 * 3)()
+        _check(lib().fde_autotune(self._h, ch), False)
+        return list(ch)
 
     def time_pass(self, which, reps=20):
         """(mean microseconds per launch, algorithmic bytes per launch) of pass `which`."""

@@ -262,3 +262,39 @@ def test_graph_replays_match_eager_launches(monkeypatch):
     for (i1, x1, y1), (i0, x0, y0) in zip(outs["1"], outs["0"]):
         assert i1 == i0
         assert np.array_equal(x1, x0) and np.array_equal(y1, y0)
+
+
+@pytest.mark.parametrize("tiles", ["1,1,1", "2,2,2", "0,2,1"])
+@pytest.mark.parametrize("kind", ["headline_24x16x8", "radix3_192x96x12", "long_1024x8x4"])
+def test_tile_variants_match_oracle(monkeypatch, tiles, kind):
+    """Every column-tile variant the autotuner may pick gives the oracle's results."""
+    banner("tiles", tiles, kind)
+    monkeypatch.setenv("FDE_TILES", tiles)
+    w = make(kind).replace(rho=1.3, delta=0.6)
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    tab = pc.precond_tables(w, d)
+    v = W.random_field(w.shape, 5)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        y = zeros(w.shape)
+        ctx.apply_S(dev(v), y)
+        z = zeros(w.shape)
+        ctx.precond(dev(v), z)
+        gs, gz = host(y), host(z)
+    assert rel(gs, admm.apply_S(d, sc, v)) <= 1e-11
+    assert rel(gz, pc.apply_precond(tab, v)) <= 1e-11
+
+
+def test_autotune_then_solve_matches_oracle():
+    banner("autotune")
+    w = W.small_mixed(nx=24, ny=16, nt=8)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        ch = ctx.autotune()
+        assert ch[0] >= 1 and 0 <= ch[1] <= 2 and 0 <= ch[2] <= 2
+        assert ctx.autotune() == ch  # cached
+        state, stats, status = ctx.admm_solve(dev(w.yhat))
+        y = host(state["y"])
+    ref = admm.admm_solve(w, iters=stats["admm_iters"])
+    assert rel(y, ref.y) <= 1e-7
