@@ -269,8 +269,10 @@ fde_status sync_scalars(fde_ctx* c) {
   return wait_readback(c);
 }
 
-// One PCG iteration (13 launches): q = S p ; alpha ; x += alpha p, r -= alpha q,
-// (r, r) and the convergence test ; z = S~^{-1} r ; (r, z) ; beta ; p = z + beta p.
+// One PCG iteration (11 launches): q = S p with (p, q) partials ; alpha inside
+// the next pass, which also does x += alpha p, r -= alpha q and (r, r) ; the
+// convergence test inside the following pass ; z = S~^{-1} r ; (r, z) ; beta ;
+// p = z + beta p.
 // Every kernel returns at once when the device flag says the solve is done.
 hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   using namespace fde;
@@ -278,7 +280,6 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   int nbS = 0, nb1 = 0, nb5 = 0;
   hipError_t e;
   if ((e = apply_S(c, c->pk, c->q, c->part_pq, done, &nbS)) != hipSuccess) return e;
-  if ((e = launch_pcg_scalar(FIN_ALPHA, c->part_pq, nbS, c->scal, c->ints, c->stream)) != hipSuccess) return e;
   PrecondArgs a = pre_args(c, c->r, c->z);
   a.q = c->q;
   a.xvec = x;
@@ -286,8 +287,13 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   a.partial = c->part_rr;
   a.partial2 = c->part_rz;
   a.done = done;
+  a.pq_partial = c->part_pq;  // alpha computed inside the x-forward pass
+  a.pq_n = nbS;
+  a.scal_w = c->scal;
+  a.ints = c->ints;
   if ((e = launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5)) != hipSuccess) return e;
-  if ((e = launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream)) != hipSuccess) return e;
+  a.rr_partial = c->part_rr;  // convergence test inside the y-forward pass
+  a.rr_n = nb1;
   if ((e = launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5)) != hipSuccess) return e;
   if ((e = launch_pcg_scalar(FIN_BETA, c->part_rz, nb5, c->scal, c->ints, c->stream)) != hipSuccess) return e;
   return launch_axpy_dot(VEC_PUPDATE, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr);

@@ -78,6 +78,13 @@ struct PrecondArgs {
   double* partial;        // x-forward: partial sums of r.r (fused mode only)
   double* partial2;       // x-inverse: partial sums of r.z (nullptr: none)
   const int* done;
+  // fused PCG scalar steps (nullptr: not fused)
+  const double* pq_partial;  // x-forward: alpha = rz / sum(pq_partial[0..pq_n))
+  int pq_n;
+  const double* rr_partial;  // y-forward: (r, r) = sum(rr_partial[0..rr_n)), convergence test
+  int rr_n;
+  double* scal_w;            // device scalars written by block 0 (alpha, pq, rr)
+  int* ints;                 // device flags written by block 0 (done, iteration count, convergence)
 };
 
 // stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5; 11..15: pass 1..5 alone

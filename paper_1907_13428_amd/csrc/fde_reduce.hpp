@@ -23,6 +23,21 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
+// Sum of p[0..n) in a fixed order (independent of the calling block), made
+// available to every thread of the block.  All threads must call.
+template <int NT>
+__device__ __forceinline__ double block_ordered_sum(const double* __restrict__ p, int n) {
+  __shared__ double bcast;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+  s = block_sum<NT>(s);
+  if (threadIdx.x == 0) bcast = s;
+  __syncthreads();
+  const double r = bcast;
+  __syncthreads();
+  return r;
+}
+
 // NaN-propagating max of non-negative values
 __device__ __forceinline__ double nanmax(double a, double b) {
   return (b > a || b != b) ? b : a;

@@ -45,7 +45,19 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   LineLds<V> buf{lds + g * lpad_size(L), 1};
   const V* tw = reinterpret_cast<const V*>(a.twx);
   double alpha = 0.0;
-  if constexpr (FUSE) alpha = a.scal[kAlpha];
+  if constexpr (FUSE) {
+    if (a.pq_partial) {
+      // alpha = (r, z) / (p, q), every block summing the partials in the same order
+      const double pq = block_ordered_sum<kPreThreads>(a.pq_partial, a.pq_n);
+      alpha = a.scal[kRZ] / pq;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.scal_w[kPQ] = pq;
+        a.scal_w[kAlpha] = alpha;
+      }
+    } else {
+      alpha = a.scal[kAlpha];
+    }
+  }
 
   V v[E];
   double rr = 0.0;
@@ -127,6 +139,28 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   __shared__ V lds[lpad_size(L) * RS];
   if (a.done && *a.done) return;
+  if constexpr (MODE == 0 && SIGN < 0) {
+    if (a.rr_partial) {
+      // PCG convergence test on the recursively updated residual (fused).
+      // Every block sums the same partials in the same order, so all reach
+      // the same verdict on convergence; only block 0 reads and advances the
+      // iteration count and records the verdict (the iteration limit stops
+      // the later kernels of this iteration through the done flag).
+      const double rr = block_ordered_sum<NT>(a.rr_partial, a.rr_n);
+      const double bb = a.scal[kBB], tol2 = a.scal[kTol2];
+      const int conv = (rr != rr) ? -1 : (rr <= tol2 * bb ? 1 : 0);
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int it = a.ints[kIter] + 1;
+        a.scal_w[kRR] = rr;
+        a.ints[kIter] = it;
+        if (conv != 0 || it >= a.ints[kMaxit]) {
+          a.ints[kConv] = conv;
+          a.ints[kDone] = 1;
+        }
+      }
+      if (conv != 0) return;
+    }
+  }
   const int H = a.H;
   const int tiles = (H + P - 1) / P;
   const int outer = blockIdx.x / tiles;  // MODE 0: time slice; MODE 1: ky row

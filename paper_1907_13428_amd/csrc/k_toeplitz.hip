@@ -20,11 +20,22 @@ namespace fde {
 
 constexpr int kLineThreads = 256;
 
+// occupancy hint of the line passes (minimum waves per SIMD the register
+// allocation must allow); 0 leaves the compiler's choice
+#ifndef FDE_LINE_WAVES
+#define FDE_LINE_WAVES 0
+#endif
+#if FDE_LINE_WAVES > 0
+#define FDE_LINE_OCC __attribute__((amdgpu_waves_per_eu(FDE_LINE_WAVES)))
+#else
+#define FDE_LINE_OCC
+#endif
+
 // ---------------------------------------------------------------------------
 // x-pass: contiguous lines (t, j), with the time difference fused
 // ---------------------------------------------------------------------------
 template <int L, bool VAR, bool TRANS>
-__global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
+__global__ __launch_bounds__(kLineThreads) FDE_LINE_OCC void k_xpass(LinePassArgs a) {
   constexpr int E = default_E(L);
   constexpr int T = L / E;
   static_assert(T <= kLineThreads, "line too long for one block");
@@ -125,8 +136,8 @@ template <int L, int S = 0> struct YCfg {
   static constexpr int E = default_E(L);
   static constexpr int T = L / E;
   static constexpr int cap(int a, int b) { return a < b ? a : b; }
-  // widest tile: at most 8 column pairs, at most 256 threads, LDS tile within 128 KiB
-  static constexpr int Pmax = cap(cap(8, kLineThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
+  // widest tile: at most 8 column pairs, at most 512 threads, LDS tile within 128 KiB
+  static constexpr int Pmax = cap(cap(8, 2 * kLineThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
   static constexpr int P = (Pmax >> S) > 0 ? (Pmax >> S) : 1;
   static constexpr int NT = ((P * T + 63) / 64) * 64;  // threads per block
   static constexpr int RS = P + 1;                     // LDS row stride (spare column P)
@@ -134,7 +145,7 @@ template <int L, int S = 0> struct YCfg {
 };
 
 template <int L, bool VAR, bool TRANS, int S>
-__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
+__global__ __launch_bounds__((YCfg<L, S>::NT)) FDE_LINE_OCC void k_ypass(LinePassArgs a) {
   using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   constexpr int n = L / 2;
