@@ -24,6 +24,9 @@
  *     tensor's data_ptr()); pointers marked (host) are host memory.  The
  *     library never frees caller memory.  A context owns only its O(n)
  *     tables and its workspace (about 12 fields plus a half spectrum).
+ *     Device fields must be 16-byte aligned (the kernels move adjacent
+ *     pairs of doubles; any hipMalloc or torch allocation is); a misaligned
+ *     field is rejected with FDE_EINVAL before any device work.
  *   - Work is enqueued on the context's stream.  Calls returning host
  *     results (iteration counts, stats) synchronise that stream; the others
  *     are asynchronous.  A context must be used by one host thread and one

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -40,6 +41,19 @@ int fail(int code, const std::string& msg) {
     hipError_t _e = (expr);                                                             \
     if (_e != hipSuccess)                                                               \
       return (fde_status)fail(FDE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// device fields are read and written in 16-byte pairs
+bool misaligned(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (p && (reinterpret_cast<uintptr_t>(p) & 15u)) return true;
+  return false;
+}
+
+#define CHECK_ALIGNED(fn, ...)                                                                \
+  do {                                                                                        \
+    if (misaligned({__VA_ARGS__}))                                                            \
+      return (fde_status)fail(FDE_EINVAL, fn ": device fields must be 16-byte aligned");    \
   } while (0)
 
 double now() {
@@ -465,6 +479,7 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
 
 fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* g, double* y, double* u, double* zy,
                       double* zu, double* p, double* wy, double* wu) {
+  CHECK_ALIGNED("fde_admm_solve", yhat, g, y, u, zy, zu, p, wy, wu);
   const auto& s = c->su;
   const fde_admm_params& q = c->prm;
   *R = AdmmRun{};
@@ -938,6 +953,7 @@ fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm) {
 fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) {
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_A: null or aliased fields");
+  CHECK_ALIGNED("fde_apply_A", x, y);
   const bool tr = transpose != 0;
   const double sti = 1.0 / ctx->su.ht;
   HIP_TRY(xpass(ctx, x, ctx->fa, tr, sti, -1.0, nullptr));
@@ -948,6 +964,7 @@ fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) 
 fde_status fde_apply_S(fde_ctx* ctx, const double* x, double* y) {
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_S: null or aliased fields");
+  CHECK_ALIGNED("fde_apply_S", x, y);
   HIP_TRY(apply_S(ctx, x, y, nullptr, nullptr, nullptr));
   return FDE_OK;
 }
@@ -955,6 +972,7 @@ fde_status fde_apply_S(fde_ctx* ctx, const double* x, double* y) {
 fde_status fde_precond(fde_ctx* ctx, const double* r, double* z) {
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!r || !z) return (fde_status)fail(FDE_EINVAL, "fde_precond: null field");
+  CHECK_ALIGNED("fde_precond", r, z);
   fde::PrecondArgs a = pre_args(ctx, const_cast<double*>(r), z);  // r is only read (no fused update)
   HIP_TRY(fde::launch_precond(a, ctx->fp32, ctx->stream, nullptr, nullptr));
   return FDE_OK;
@@ -963,6 +981,7 @@ fde_status fde_precond(fde_ctx* ctx, const double* r, double* z) {
 fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, double* relres) {
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!b || !x || b == x) return (fde_status)fail(FDE_EINVAL, "fde_krylov: null or aliased fields");
+  CHECK_ALIGNED("fde_krylov", b, x);
   int it = 0;
   double rr = 0;
   const fde_status st = krylov(ctx, b, x, ctx->prm.krylov_tol, ctx->prm.krylov_maxit, &it, &rr, 0);
@@ -1103,6 +1122,7 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   using namespace fde;
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (!yhat || !y || !p || !dab) return (fde_status)fail(FDE_EINVAL, "fde_grad: null argument");
+  CHECK_ALIGNED("fde_grad", yhat, y, p, wy, dyhat, lambda_out);
   fde_ctx* c = ctx;
   double* lam = lambda_out ? lambda_out : c->z;
   if (adjoint_solve) {

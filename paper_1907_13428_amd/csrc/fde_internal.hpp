@@ -13,6 +13,10 @@ namespace fde {
 constexpr int kBlock = 256;        // threads per block of the elementwise / reduction kernels
 constexpr int kMaxPartials = 4096;  // partial-sum slots per reduction
 
+// 16-byte accesses of two adjacent doubles (fields are 16-byte aligned and nx is even)
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+
 // ---------------------------------------------------------------------------
 // Toeplitz line passes (operator D and D^T)
 //

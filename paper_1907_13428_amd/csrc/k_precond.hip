@@ -181,11 +181,27 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   const int g = active ? tid / T : P, t = tid % T;
   LineLds<V> buf{lds + g, RS};
 
-  for (int idx = tid; idx < L * P; idx += NT) {
+  // tile load: all loads of a thread are issued before the first LDS store;
+  // elements outside the tile or the plane read the tile's first element
+  // (always inside) and are zeroed after the load
+  constexpr int NE = L * P;
+  constexpr int KL = (NE + NT - 1) / NT;
+  auto elem = [&](int k, bool& ok) -> size_t {
+    const int idx = tid + k * NT;
     const int row = idx / P, c = idx % P;
-    V val = V{TS(0), TS(0)};
-    if (k0 + c < H) val = spec[base + row * stride + k0 + c];
-    lds[lpad(row) * RS + c] = val;
+    ok = idx < NE && k0 + c < H;
+    return base + (ok ? row * stride + c : 0) + k0;
+  };
+  {
+    V lv[KL];
+    bool ok[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) lv[k] = spec[elem(k, ok[k])];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int idx = tid + k * NT;
+      if (idx < NE) lds[lpad(idx / P) * RS + idx % P] = ok[k] ? lv[k] : V{TS(0), TS(0)};
+    }
   }
   __syncthreads();
   V v[E];
@@ -227,9 +243,12 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
     for (int e = 0; e < E; ++e) buf[t + T * e] = v[e];
   }
   __syncthreads();
-  for (int idx = tid; idx < L * P; idx += NT) {
-    const int row = idx / P, c = idx % P;
-    if (k0 + c < H) spec[base + row * stride + k0 + c] = lds[lpad(row) * RS + c];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    bool ok;
+    const size_t gi = elem(k, ok);
+    const int idx = tid + k * NT;
+    if (ok) spec[gi] = lds[lpad(idx / P) * RS + idx % P];
   }
 }
 

@@ -20,22 +20,12 @@ namespace fde {
 
 constexpr int kLineThreads = 256;
 
-// occupancy hint of the line passes (minimum waves per SIMD the register
-// allocation must allow); 0 leaves the compiler's choice
-#ifndef FDE_LINE_WAVES
-#define FDE_LINE_WAVES 0
-#endif
-#if FDE_LINE_WAVES > 0
-#define FDE_LINE_OCC __attribute__((amdgpu_waves_per_eu(FDE_LINE_WAVES)))
-#else
-#define FDE_LINE_OCC
-#endif
 
 // ---------------------------------------------------------------------------
 // x-pass: contiguous lines (t, j), with the time difference fused
 // ---------------------------------------------------------------------------
 template <int L, bool VAR, bool TRANS>
-__global__ __launch_bounds__(kLineThreads) FDE_LINE_OCC void k_xpass(LinePassArgs a) {
+__global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   constexpr int E = default_E(L);
   constexpr int T = L / E;
   static_assert(T <= kLineThreads, "line too long for one block");
@@ -145,7 +135,7 @@ template <int L, int S = 0> struct YCfg {
 };
 
 template <int L, bool VAR, bool TRANS, int S>
-__global__ __launch_bounds__((YCfg<L, S>::NT)) FDE_LINE_OCC void k_ypass(LinePassArgs a) {
+__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   constexpr int n = L / 2;
@@ -158,7 +148,6 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) FDE_LINE_OCC void k_ypass(LinePas
   const int slice = blockIdx.x / tiles;
   const int x0 = (blockIdx.x % tiles) * TX;
   const size_t sbase = (size_t)slice * n * nx;
-  double* ldsd = reinterpret_cast<double*>(lds);
   const int tid = threadIdx.x;
   // threads beyond P*T (block rounded up to whole wavefronts) run the FFT on
   // the spare LDS column P, which holds no data, and store nothing
@@ -166,22 +155,49 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) FDE_LINE_OCC void k_ypass(LinePas
   const int g = active ? tid / T : P, t = tid % T;
   LineLds<double2> buf{lds + g, RS};
 
-  // cooperative tile load (rows 0..n-1; transposed-variable case also d- v in rows n..2n-1)
-  for (int idx = tid; idx < n * TX; idx += NT) {
-    const int row = idx / TX, c = idx % TX, x = x0 + c;
-    double val = 0.0;
-    double val2 = 0.0;
-    if (x < nx) {
-      const double vin = a.in[sbase + (size_t)row * nx + x];
-      if constexpr (VAR && TRANS) {
-        val = a.dplus[row * nx + x] * vin;
-        val2 = a.dminus[row * nx + x] * vin;
-      } else {
-        val = vin;
+  // Cooperative tile load, element = (row, column pair): one 16-byte access per
+  // element (nx is even and tiles start at even columns, so a pair never
+  // straddles the edge).  Elements outside the tile or the grid read the
+  // tile's first pair (always inside) and are zeroed after the load, so a
+  // thread issues all its loads before the first LDS store, without branches.
+  // Rows 0..n-1 hold v (d+ v in the transposed variable case, with d- v in
+  // rows n..2n-1); columns beyond nx are zero.
+  constexpr int NE = n * P;
+  constexpr int KL = (NE + NT - 1) / NT;
+  int ge[KL];     // offset of the element within the slice (plane index)
+  bool ok[KL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const int idx = tid + k * NT;
+    const int row = idx / P, x = x0 + 2 * (idx % P);
+    ok[k] = idx < NE && x < nx;
+    ge[k] = ok[k] ? row * nx + x : x0;
+  }
+  {
+    double2 lv[KL], lp[KL], lm[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) lv[k] = ld2(a.in + sbase + ge[k]);
+    if constexpr (VAR && TRANS) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        lp[k] = ld2(a.dplus + ge[k]);
+        lm[k] = ld2(a.dminus + ge[k]);
       }
     }
-    ldsd[2 * (lpad(row) * RS + (c >> 1)) + (c & 1)] = val;
-    if constexpr (VAR && TRANS) ldsd[2 * (lpad(row + n) * RS + (c >> 1)) + (c & 1)] = val2;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int idx = tid + k * NT;
+      if (idx < NE) {
+        const int row = idx / P, cp = idx % P;
+        const double2 v0 = ok[k] ? lv[k] : double2{0.0, 0.0};
+        if constexpr (VAR && TRANS) {
+          lds[lpad(row) * RS + cp] = double2{lp[k].x * v0.x, lp[k].y * v0.y};
+          lds[lpad(row + n) * RS + cp] = double2{lm[k].x * v0.x, lm[k].y * v0.y};
+        } else {
+          lds[lpad(row) * RS + cp] = v0;
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -226,24 +242,46 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) FDE_LINE_OCC void k_ypass(LinePas
   }
   __syncthreads();
 
+  // epilogue: all global operands of a thread are loaded before the first store
   const double osc = a.oscale ? a.oscale[slice] : 1.0;
   const double esc = a.extra ? a.escale[slice] : 0.0;
   double dot = 0.0;
-  for (int idx = tid; idx < n * TX; idx += NT) {
-    const int row = idx / TX, c = idx % TX, x = x0 + c;
-    if (x >= nx) continue;
-    double sp = ldsd[2 * (lpad(row) * RS + (c >> 1)) + (c & 1)];
-    if constexpr (VAR && !TRANS) {
-      const double sp2 = ldsd[2 * (lpad(row + n) * RS + (c >> 1)) + (c & 1)];
-      sp = a.dplus[row * nx + x] * sp + a.dminus[row * nx + x] * sp2;
+  {
+    const double2 z2{0.0, 0.0};
+    double2 sp[KL], ac[KL], ex[KL], dv[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int idx = tid + k * NT;
+      const int li = ok[k] ? lpad(idx / P) * RS + idx % P : 0;
+      sp[k] = lds[li];
+      if constexpr (VAR && !TRANS) {
+        const double2 s2 = lds[ok[k] ? lpad(idx / P + n) * RS + idx % P : 0];
+        const double2 dp = ld2(a.dplus + ge[k]), dm = ld2(a.dminus + ge[k]);
+        sp[k] = double2{dp.x * sp[k].x + dm.x * s2.x, dp.y * sp[k].y + dm.y * s2.y};
+      }
+      ac[k] = ex[k] = dv[k] = z2;
     }
-    const size_t gi = sbase + (size_t)row * nx + x;
-    double val = a.s_sp * sp;
-    if (a.acc) val += a.acc[gi];
-    val *= osc;
-    if (a.extra) val += esc * a.extra[gi];
-    a.out[gi] = val;
-    if (a.dotv) dot += a.dotv[gi] * val;
+    if (a.acc) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) ac[k] = ld2(a.acc + sbase + ge[k]);
+    }
+    if (a.extra) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) ex[k] = ld2(a.extra + sbase + ge[k]);
+    }
+    if (a.dotv) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) dv[k] = ld2(a.dotv + sbase + ge[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      if (ok[k]) {
+        const double2 val{(a.s_sp * sp[k].x + ac[k].x) * osc + esc * ex[k].x,
+                          (a.s_sp * sp[k].y + ac[k].y) * osc + esc * ex[k].y};
+        st2(a.out + sbase + ge[k], val);
+        dot += dv[k].x * val.x + dv[k].y * val.y;
+      }
+    }
   }
   if (a.dotv) {
     const double s = block_sum<NT>(dot);

@@ -142,6 +142,27 @@ def test_krylov_zero_rhs_returns_zero():
         assert np.all(host(x) == 0.0)
 
 
+def test_misaligned_fields_are_rejected_before_device_work():
+    banner("misaligned fields")
+    w = make("small")
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        buf = zeros((w.N + 1,))
+        bad = buf[1:].view(w.shape)  # 8-byte offset
+        y = zeros(w.shape)
+        with pytest.raises(fde.FdeError) as e:
+            ctx.apply_S(bad, y)
+        assert e.value.status == fde.FDE_EINVAL and "16-byte aligned" in str(e.value)
+        with pytest.raises(fde.FdeError) as e:
+            state = {k: zeros(w.shape) for k in ("u", "zy", "zu", "p", "wy", "wu")}
+            state["y"] = bad
+            ctx.admm_solve(dev(w.yhat), state=state)
+        assert e.value.status == fde.FDE_EINVAL
+        # the context is still usable
+        ctx.apply_S(dev(W.random_field(w.shape, 2)), y)
+        assert np.isfinite(host(y)).all()
+
+
 def test_krylov_maxit_reports_not_converged():
     banner("krylov maxit")
     w = make("small").replace(krylov_maxit=2, krylov_tol=1e-14)
