@@ -59,32 +59,52 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
     }
   }
 
+  // Input lines (with the fused update).  Loads are issued in groups of G
+  // elements before the group's stores (the fields may alias as far as the
+  // compiler knows, so it cannot hoist them itself); a missing line reads
+  // line 0 and is zeroed.
+  constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
+  const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
   V v[E];
   double rr = 0.0;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + T * e;
-    double r0 = 0.0, r1 = 0.0;
-    if (h0) {
-      const size_t gi = (size_t)l0 * L + i;
-      r0 = a.r[gi];
+  for (int e0 = 0; e0 < E; e0 += G) {
+    double r0[G], r1[G], q0[G], q1[G], x0[G], x1[G], p0[G], p1[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int i = t + T * (e0 + k);
+      r0[k] = a.r[b0 + i];
+      r1[k] = a.r[b1 + i];
       if constexpr (FUSE) {
-        r0 -= alpha * a.q[gi];
-        a.r[gi] = r0;
-        a.xvec[gi] += alpha * a.pvec[gi];
+        q0[k] = a.q[b0 + i];
+        q1[k] = a.q[b1 + i];
+        x0[k] = a.xvec[b0 + i];
+        x1[k] = a.xvec[b1 + i];
+        p0[k] = a.pvec[b0 + i];
+        p1[k] = a.pvec[b1 + i];
       }
     }
-    if (h1) {
-      const size_t gi = (size_t)l1 * L + i;
-      r1 = a.r[gi];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int i = t + T * (e0 + k);
+      double s0 = r0[k], s1 = r1[k];
       if constexpr (FUSE) {
-        r1 -= alpha * a.q[gi];
-        a.r[gi] = r1;
-        a.xvec[gi] += alpha * a.pvec[gi];
+        s0 -= alpha * q0[k];
+        s1 -= alpha * q1[k];
+        if (h0) {
+          a.r[b0 + i] = s0;
+          a.xvec[b0 + i] = x0[k] + alpha * p0[k];
+        }
+        if (h1) {
+          a.r[b1 + i] = s1;
+          a.xvec[b1 + i] = x1[k] + alpha * p1[k];
+        }
       }
+      if (!h0) s0 = 0.0;
+      if (!h1) s1 = 0.0;
+      rr += s0 * s0 + s1 * s1;
+      v[e0 + k] = V{TS(s0), TS(s1)};
     }
-    rr += r0 * r0 + r1 * r1;
-    v[e] = V{TS(r0), TS(r1)};
   }
   if constexpr (FUSE) {
     const double s = block_sum<kPreThreads>(rr);
@@ -289,21 +309,34 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
     v[e] = V{x1.x - x2.y, x1.y + x2.x};  // X1 + i X2
   }
   line_fft<L, E, +1>(v, buf, t, tw);
+  // z out, with (r, z): the r loads of a group of G elements are issued before
+  // the group's stores; a missing line reads line 0 and contributes nothing
+  constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
+  const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
   double rz = 0.0;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + T * e;
-    if (h0) {
-      const size_t gi = (size_t)l0 * L + i;
-      const double z0 = double(v[e].x);
-      a.z[gi] = z0;
-      if constexpr (DOT) rz += a.r[gi] * z0;
+  for (int e0 = 0; e0 < E; e0 += G) {
+    double r0[G], r1[G];
+    if constexpr (DOT) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int i = t + T * (e0 + k);
+        r0[k] = a.r[b0 + i];
+        r1[k] = a.r[b1 + i];
+      }
     }
-    if (h1) {
-      const size_t gi = (size_t)l1 * L + i;
-      const double z1 = double(v[e].y);
-      a.z[gi] = z1;
-      if constexpr (DOT) rz += a.r[gi] * z1;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int i = t + T * (e0 + k);
+      const double z0 = double(v[e0 + k].x), z1 = double(v[e0 + k].y);
+      if (h0) {
+        a.z[b0 + i] = z0;
+        if constexpr (DOT) rz += r0[k] * z0;
+      }
+      if (h1) {
+        a.z[b1 + i] = z1;
+        if constexpr (DOT) rz += r1[k] * z1;
+      }
     }
   }
   if constexpr (DOT) {

@@ -86,33 +86,72 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   line_fft<L, E, +1>(v, buf, t, a.tw);
   if constexpr (VAR && !TRANS) line_fft<L, E, +1>(w, buf, t, a.tw);
 
-  // epilogue: out = s_time * time difference + s_sp * spatial
+  // Epilogue, out = s_time * time difference + s_sp * spatial, through the
+  // pair's LDS buffer: thread t then owns adjacent elements (i, i+1) of both
+  // lines (16-byte accesses; n is even) and issues all loads of a group of
+  // element pairs before its first store.  Missing lines and time neighbours
+  // read an address inside the field and are zeroed after the load.
+  constexpr bool WAVE = T <= 64;
+  line_sync<WAVE>();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = t + T * e;
-    if (i >= n) continue;
+    if (i < n) {
+      buf[i] = v[e];
+      if constexpr (VAR && !TRANS) buf[i + n] = w[e];
+    }
+  }
+  line_sync<WAVE>();
+
+  constexpr int KE = E / 4;                    // element pairs per thread (n / 2 = T E / 4)
+  constexpr int KG = (KE % 2 == 0) ? 2 : KE;   // element pairs per load group
+  const size_t plane = (size_t)a.ny * n;
+  const int tt0 = l0 / a.ny, tt1 = l1 / a.ny;
+  const bool nb0 = h0 && (TRANS ? tt0 + 1 < a.nt : tt0 > 0);
+  const bool nb1 = h1 && (TRANS ? tt1 + 1 < a.nt : tt1 > 0);
+  const size_t b0 = h0 ? (size_t)l0 * n : 0, b1 = h1 ? (size_t)l1 * n : 0;
+  const ptrdiff_t nbo0 = nb0 ? (TRANS ? (ptrdiff_t)plane : -(ptrdiff_t)plane) : 0;
+  const ptrdiff_t nbo1 = nb1 ? (TRANS ? (ptrdiff_t)plane : -(ptrdiff_t)plane) : 0;
+  const int r0 = h0 ? (l0 % a.ny) * n : 0, r1 = h1 ? (l1 % a.ny) * n : 0;
+  const bool timed = a.s_time != 0.0;
+  const double2 z2{0.0, 0.0};
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int l = h ? l1 : l0;
-      if (!(h ? h1 : h0)) continue;
-      double sp = h ? v[e].y : v[e].x;
+  for (int k0 = 0; k0 < KE; k0 += KG) {
+    double2 c0[KG], c1[KG], p0[KG], p1[KG], dp0[KG], dp1[KG], dm0[KG], dm1[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int i = 2 * (t + T * (k0 + k));
+      c0[k] = c1[k] = p0[k] = p1[k] = z2;
+      if (timed) {
+        c0[k] = ld2(in + b0 + i);
+        c1[k] = ld2(in + b1 + i);
+        p0[k] = ld2(in + b0 + i + nbo0);
+        p1[k] = ld2(in + b1 + i + nbo1);
+      }
       if constexpr (VAR && !TRANS) {
-        const int j = l % a.ny;
-        sp = a.dplus[j * n + i] * sp + a.dminus[j * n + i] * (h ? w[e].y : w[e].x);
+        dp0[k] = ld2(a.dplus + r0 + i);
+        dm0[k] = ld2(a.dminus + r0 + i);
+        dp1[k] = ld2(a.dplus + r1 + i);
+        dm1[k] = ld2(a.dminus + r1 + i);
       }
-      const size_t gi = (size_t)l * n + i;
-      double val = a.s_sp * sp;
-      if (a.s_time != 0.0) {
-        const int tt = l / a.ny;
-        double nb = 0.0;
-        if constexpr (TRANS) {
-          if (tt + 1 < a.nt) nb = in[gi + (size_t)a.ny * n];
-        } else {
-          if (tt > 0) nb = in[gi - (size_t)a.ny * n];
-        }
-        val += a.s_time * (in[gi] - nb);
+    }
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int i = 2 * (t + T * (k0 + k));
+      const double2 sa = buf[i], sb = buf[i + 1];
+      double2 s0{sa.x, sb.x}, s1{sa.y, sb.y};  // spatial products of lines l0, l1
+      if constexpr (VAR && !TRANS) {
+        const double2 ta = buf[i + n], tb = buf[i + n + 1];
+        s0 = double2{dp0[k].x * s0.x + dm0[k].x * ta.x, dp0[k].y * s0.y + dm0[k].y * tb.x};
+        s1 = double2{dp1[k].x * s1.x + dm1[k].x * ta.y, dp1[k].y * s1.y + dm1[k].y * tb.y};
       }
-      a.out[gi] = val;
+      const double2 q0 = nb0 ? p0[k] : z2, q1 = nb1 ? p1[k] : z2;
+      if (h0)
+        st2(a.out + b0 + i, double2{a.s_sp * s0.x + a.s_time * (c0[k].x - q0.x),
+                                    a.s_sp * s0.y + a.s_time * (c0[k].y - q0.y)});
+      if (h1)
+        st2(a.out + b1 + i, double2{a.s_sp * s1.x + a.s_time * (c1[k].x - q1.x),
+                                    a.s_sp * s1.y + a.s_time * (c1[k].y - q1.y)});
     }
   }
 }
