@@ -13,6 +13,17 @@ namespace fde {
 constexpr int kBlock = 256;        // threads per block of the elementwise / reduction kernels
 constexpr int kMaxPartials = 4096;  // partial-sum slots per reduction
 
+// Logical tile of block b (of nb): the hardware hands consecutive blocks to
+// the 8 XCDs in turn, each XCD with its own L2; this bijection gives each XCD
+// a contiguous run of tiles, so neighbouring tiles that share cache lines or
+// DRAM pages run under one L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  const int x = b % kXcd, k = b / kXcd;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // 16-byte accesses of two adjacent doubles (fields are 16-byte aligned and nx is even)
 __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
 __device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }

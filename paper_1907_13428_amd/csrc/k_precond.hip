@@ -183,8 +183,9 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   }
   const int H = a.H;
   const int tiles = (H + P - 1) / P;
-  const int outer = blockIdx.x / tiles;  // MODE 0: time slice; MODE 1: ky row
-  const int k0 = (blockIdx.x % tiles) * P;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int outer = tile / tiles;  // MODE 0: time slice; MODE 1, 2: ky row
+  const int k0 = (tile % tiles) * P;
   // element (line index i, column c) address in the spectrum
   size_t base, stride;
   if (MODE == 0) {

@@ -42,28 +42,30 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   LineLds<double2> buf{lds + g * lpad_size(L), 1};
   const double* __restrict__ in = a.in;
 
+  // element e of thread t is i = t + T e; i < n exactly when e < EH, so the
+  // zero half of the embedding and the discarded half of the result are
+  // known at compile time
+  constexpr int EH = E / 2;
   double2 v[E];
   double2 w[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
+  for (int e = 0; e < EH; ++e) {
     const int i = t + T * e;
     double x0 = 0.0, x1 = 0.0;
-    if (i < n) {
-      if (h0) x0 = in[(size_t)l0 * n + i];
-      if (h1) x1 = in[(size_t)l1 * n + i];
-    }
+    if (h0) x0 = in[(size_t)l0 * n + i];
+    if (h1) x1 = in[(size_t)l1 * n + i];
     if constexpr (VAR && TRANS) {
       double p0 = 0, p1 = 0, m0 = 0, m1 = 0;
-      if (i < n) {
-        if (h0) { p0 = a.dplus[(l0 % a.ny) * n + i]; m0 = a.dminus[(l0 % a.ny) * n + i]; }
-        if (h1) { p1 = a.dplus[(l1 % a.ny) * n + i]; m1 = a.dminus[(l1 % a.ny) * n + i]; }
-      }
+      if (h0) { p0 = a.dplus[(l0 % a.ny) * n + i]; m0 = a.dminus[(l0 % a.ny) * n + i]; }
+      if (h1) { p1 = a.dplus[(l1 % a.ny) * n + i]; m1 = a.dminus[(l1 % a.ny) * n + i]; }
       v[e] = double2{p0 * x0, p1 * x1};
       w[e] = double2{m0 * x0, m1 * x1};
     } else {
       v[e] = double2{x0, x1};
     }
   }
+#pragma unroll
+  for (int e = EH; e < E; ++e) v[e] = w[e] = double2{0.0, 0.0};
 
   line_fft<L, E, -1>(v, buf, t, a.tw);
   if constexpr (VAR && TRANS) line_fft<L, E, -1>(w, buf, t, a.tw);
@@ -94,12 +96,9 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   constexpr bool WAVE = T <= 64;
   line_sync<WAVE>();
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + T * e;
-    if (i < n) {
-      buf[i] = v[e];
-      if constexpr (VAR && !TRANS) buf[i + n] = w[e];
-    }
+  for (int e = 0; e < EH; ++e) {
+    buf[t + T * e] = v[e];
+    if constexpr (VAR && !TRANS) buf[t + T * e + n] = w[e];
   }
   line_sync<WAVE>();
 
@@ -184,8 +183,9 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 
   const int nx = a.nx;
   const int tiles = (nx + TX - 1) / TX;
-  const int slice = blockIdx.x / tiles;
-  const int x0 = (blockIdx.x % tiles) * TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int slice = tile / tiles;
+  const int x0 = (tile % tiles) * TX;
   const size_t sbase = (size_t)slice * n * nx;
   const int tid = threadIdx.x;
   // threads beyond P*T (block rounded up to whole wavefronts) run the FFT on
@@ -240,13 +240,17 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   }
   __syncthreads();
 
+  // element e of thread t is row i = t + T e; i < n exactly when e < EH
+  constexpr int EH = E / 2;
   double2 v[E];
   double2 w[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int i = t + T * e;
-    v[e] = (i < n) ? buf[i] : double2{0.0, 0.0};
-    if constexpr (VAR && TRANS) w[e] = (i < n) ? buf[i + n] : double2{0.0, 0.0};
+    v[e] = w[e] = double2{0.0, 0.0};
+    if (e < EH) {
+      v[e] = buf[t + T * e];
+      if constexpr (VAR && TRANS) w[e] = buf[t + T * e + n];
+    }
   }
   __syncthreads();
 
@@ -271,12 +275,9 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   __syncthreads();
   if (active) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int i = t + T * e;
-      if (i < n) {
-        buf[i] = v[e];
-        if constexpr (VAR && !TRANS) buf[i + n] = w[e];
-      }
+    for (int e = 0; e < EH; ++e) {
+      buf[t + T * e] = v[e];
+      if constexpr (VAR && !TRANS) buf[t + T * e + n] = w[e];
     }
   }
   __syncthreads();
