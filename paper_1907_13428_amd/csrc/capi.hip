@@ -283,10 +283,10 @@ fde_status sync_scalars(fde_ctx* c) {
   return wait_readback(c);
 }
 
-// One PCG iteration (11 launches): q = S p with (p, q) partials ; alpha inside
+// One PCG iteration (10 launches): q = S p with (p, q) partials ; alpha inside
 // the next pass, which also does x += alpha p, r -= alpha q and (r, r) ; the
-// convergence test inside the following pass ; z = S~^{-1} r ; (r, z) ; beta ;
-// p = z + beta p.
+// convergence test inside the following pass ; z = S~^{-1} r with (r, z)
+// partials ; beta inside p = z + beta p.
 // Every kernel returns at once when the device flag says the solve is done.
 hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   using namespace fde;
@@ -309,8 +309,7 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   a.rr_partial = c->part_rr;  // convergence test inside the y-forward pass
   a.rr_n = nb1;
   if ((e = launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5)) != hipSuccess) return e;
-  if ((e = launch_pcg_scalar(FIN_BETA, c->part_rz, nb5, c->scal, c->ints, c->stream)) != hipSuccess) return e;
-  return launch_axpy_dot(VEC_PUPDATE, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr);
+  return launch_pupdate(c->N, c->z, c->pk, c->scal, c->ints, c->part_rz, nb5, done, c->stream);
 }
 
 void drop_pcg_graph(fde_ctx* c) {

@@ -113,7 +113,8 @@ inline hipError_t launch_precond(const PrecondArgs& a, bool fp32, hipStream_t s,
 // device scalar slots of the Krylov / ADMM state
 // ---------------------------------------------------------------------------
 enum ScalarSlot {
-  kRZ = 0,    // (r, z)
+  kRZ = 0,    // (r, z) of even PCG iterations (0, 2, ...)
+  kRZ1,       // (r, z) of odd iterations: the p update reads one slot and writes the other
   kPQ,        // (p, q)
   kAlpha,
   kBeta,
@@ -131,6 +132,8 @@ enum ScalarSlot {
   kNumScalars
 };
 enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kNumInts };
+// slot of (r, z) after iteration `iter` (iteration 0 = the initial residual)
+__host__ __device__ __forceinline__ int rz_slot(int iter) { return (iter & 1) ? kRZ1 : kRZ; }
 
 // elementwise / reduction kernels
 enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_ALPHA, FIN_CONV, FIN_BETA, FIN_DOT };
@@ -148,6 +151,10 @@ hipError_t launch_pcg_scalar(int op, const double* partial, int n, double* scal,
 hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, double* c,
                            const double* scal, double* partial, const int* done, hipStream_t s,
                            int* nblocks);
+// p = z + beta p with beta = (r, z)_k / (r, z)_{k-1}, (r, z)_k summed inside
+// from the partials of the z pass (every block in the same order)
+hipError_t launch_pupdate(int64_t n, const double* z, double* p, double* scal, const int* ints,
+                          const double* rz_partial, int rz_n, const int* done, hipStream_t s);
 
 struct AdmmConsts {
   int64_t n;

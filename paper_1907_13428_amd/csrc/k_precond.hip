@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
     if (a.pq_partial) {
       // alpha = (r, z) / (p, q), every block summing the partials in the same order
       const double pq = block_ordered_sum<kPreThreads>(a.pq_partial, a.pq_n);
-      alpha = a.scal[kRZ] / pq;
+      alpha = a.scal[rz_slot(a.ints[kIter])] / pq;
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.scal_w[kPQ] = pq;
         a.scal_w[kAlpha] = alpha;

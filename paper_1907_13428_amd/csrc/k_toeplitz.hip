@@ -309,7 +309,10 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 #pragma unroll
       for (int k = 0; k < KL; ++k) ex[k] = ld2(a.extra + sbase + ge[k]);
     }
-    if (a.dotv) {
+    if (a.dotv && a.dotv == a.extra) {
+#pragma unroll
+      for (int k = 0; k < KL; ++k) dv[k] = ex[k];
+    } else if (a.dotv) {
 #pragma unroll
       for (int k = 0; k < KL; ++k) dv[k] = ld2(a.dotv + sbase + ge[k]);
     }
