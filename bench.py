@@ -45,6 +45,7 @@ def parse():
                     help="ADMM iteration cap of the cold-start solves (tolerance 1e-6)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--batch-cap", type=int, default=30, help="ADMM iterations per batched instance")
+    ap.add_argument("--pass-reps", type=int, default=50, help="launches per pass for the per-pass timing")
     return ap.parse_args()
 
 
@@ -74,6 +75,59 @@ def cpu_baseline(w, iters):
     return {"value": iters / dt, "unit": "PCG iters/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{iters} PCG iterations of the oracle on the 256x256x64 headline grid "
                       f"(S apply + no-FFT preconditioner), {dt:.1f} s"}
+
+
+COPY_BYTES = 256 << 20  # plain device copy: achievable-bandwidth and counter calibration
+
+
+def copy_calibration(torch, reps=5):
+    """A plain device-to-device copy of COPY_BYTES (torch's copy kernel): the
+    achievable read+write bandwidth, and the known-size kernel against which the
+    FETCH_SIZE / WRITE_SIZE counters of the roofline traffic are scaled."""
+    n = COPY_BYTES // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * COPY_BYTES, "us": round(us, 2), "GB/s": round(2 * COPY_BYTES / us / 1e3, 1)}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ypass_BT_headline_256x256x64.json")
+KERNEL_SOURCES = ["paper_1907_13428_amd/csrc/k_toeplitz.hip", "paper_1907_13428_amd/csrc/fde_fft.hpp",
+                  "paper_1907_13428_amd/csrc/fde_internal.hpp", "paper_1907_13428_amd/csrc/fde_reduce.hpp"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(pass_name, tile_width):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes scaled by the copy kernel), or
+    None when there is none for this pass and tile or the kernel sources have
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("pass") != pass_name or rec.get("tile_width") != tile_width
+            or rec.get("source_sha256") != kernel_source_hash()):
+        return None
+    return rec.get("traffic_bytes")
 
 
 def batched_leg(fde, torch, cap):
@@ -139,12 +193,15 @@ def main():
     # ---- per-pass kernel timing (HIP events on the library stream) ---------
     passes = {}
     for i, name in enumerate(fde.PASS_NAMES):
-        us, by = ctx.time_pass(i, reps=50)
+        us, by = ctx.time_pass(i, reps=a.pass_reps)
         passes[name] = {"us": round(us, 2), "GB/s": round(by / us / 1e3, 1), "bytes": by}
     dom = max(passes, key=lambda k: passes[k]["us"])
     achieved = passes[dom]["bytes"] / passes[dom]["us"] / 1e3
+    copy = copy_calibration(torch)
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": measured_traffic(dom, out["autotune"][0]),
+                       "bytes_per_launch": passes[dom]["bytes"], "copy_kernel": copy}
     pcg_pass_us = sum(p["us"] for p in passes.values())
     pcg_bytes = sum(p["bytes"] for p in passes.values())
     out["pcg_iteration_passes"] = passes

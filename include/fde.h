@@ -196,8 +196,10 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
  * PCG iteration `reps` times back to back on the context stream between two
  * HIP events and report the mean duration per launch (*us, host) and the
  * algorithmic HBM bytes one launch must move (*bytes, host: every field the
- * pass reads or writes counted once).  The pass runs on the context's
- * workspace (contents are overwritten).  which:
+ * pass reads or writes counted once).  The field passes alternate between two
+ * disjoint sets of workspace fields, so a launch finds its inputs about as
+ * warm in the last-level cache as inside an iteration.  The pass runs on the
+ * context's workspace (contents are overwritten).  which:
  *   0 x-pass of B (time difference fused)   1 y-pass of B (scaled by M_p^-1)
  *   2 x-pass of B^T                          3 y-pass of B^T (+ M_y v, (v, Sv))
  *   4 preconditioner x-forward (fused r -= alpha q, x += alpha p, (r, r))

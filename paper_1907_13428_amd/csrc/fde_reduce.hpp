@@ -24,12 +24,23 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Sum of p[0..n) in a fixed order (independent of the calling block), made
-// available to every thread of the block.  All threads must call.
+// available to every thread of the block.  All threads must call.  Each
+// thread loads up to 8 of its strided elements at once (one L2 round trip
+// per 8 NT elements) and adds them in a fixed tree order.
 template <int NT>
 __device__ __forceinline__ double block_ordered_sum(const double* __restrict__ p, int n) {
   __shared__ double bcast;
+  constexpr int U = 8;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += NT) s += p[i];
+  for (int i0 = 0; i0 < n; i0 += U * NT) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT + (int)threadIdx.x;
+      x[u] = i < n ? p[i] : 0.0;
+    }
+    s += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+  }
   s = block_sum<NT>(s);
   if (threadIdx.x == 0) bcast = s;
   __syncthreads();

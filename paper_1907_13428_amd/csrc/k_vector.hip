@@ -12,9 +12,19 @@ namespace fde {
 __device__ __forceinline__ bool is_done(const int* done) { return done && *done; }
 
 // Sum of partial[0..n) in fixed order; valid in thread 0 of the (single) block.
+// Up to 8 strided loads per thread are in flight at once.
 __device__ __forceinline__ double ordered_sum(const double* partial, int n) {
+  constexpr int U = 8;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlock) s += partial[i];
+  for (int i0 = 0; i0 < n; i0 += U * kBlock) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kBlock + (int)threadIdx.x;
+      x[u] = i < n ? partial[i] : 0.0;
+    }
+    s += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
+  }
   return block_sum<kBlock>(s);
 }
 

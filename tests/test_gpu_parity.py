@@ -163,6 +163,31 @@ def test_misaligned_fields_are_rejected_before_device_work():
         assert np.isfinite(host(y)).all()
 
 
+def test_time_pass_then_solve():
+    """The pass timer covers all nine passes with their algorithmic byte
+    counts, rejects a bad pass, and leaves the context usable."""
+    banner("time_pass")
+    w = make("ragged_var_24x48x6")
+    prob, prm = fde.from_workload(w)
+    n8 = 8.0 * w.N
+    sb = (w.nx // 2 + 1) * w.ny * w.nt * 16.0
+    expect = [2 * n8, 3 * n8, 2 * n8, 4 * n8, 6 * n8 + sb, 2 * sb, 2 * sb, 2 * sb, 2 * n8 + sb]
+    with fde.Context(prob, prm) as ctx:
+        for i in range(9):
+            us, by = ctx.time_pass(i, 40)
+            assert us > 0 and by == expect[i], (i, us, by)
+        with pytest.raises(fde.FdeError) as e:
+            ctx.time_pass(9, 5)
+        assert e.value.status == fde.FDE_EINVAL
+        d = op.disc_from(w)
+        sc = admm.scalars(w, d)
+        b = W.random_field(w.shape, 4)
+        x = zeros(w.shape)
+        it, relres, st = ctx.krylov(dev(b), x)
+        assert st == fde.FDE_OK
+        assert rel(admm.apply_S(d, sc, host(x)), b) <= 1e-9
+
+
 def test_krylov_maxit_reports_not_converged():
     banner("krylov maxit")
     w = make("small").replace(krylov_maxit=2, krylov_tol=1e-14)
