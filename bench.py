@@ -226,7 +226,8 @@ def main():
                 rec = {"admm_solve_s": round(t, 3), "admm_iters": st2["admm_iters"], "admm_cap": a.full_cap,
                        "pcg_total": st2["pcg_total"], "pcg_iters_per_s": round(st2["pcg_total"] / t, 1),
                        "ms_per_admm_iter": round(1e3 * t / st2["admm_iters"], 3), "converged": status == 0,
-                       "residuals": [st2["r_p"], st2["r_y"], st2["r_u"]]}
+                       "residuals": [st2["r_p"], st2["r_y"], st2["r_u"]], "dual_inf": st2["dual_inf"],
+                       "J": st2["J"]}
                 if fp32:
                     rec["rel_diff_y_vs_fp64"] = float(torch.linalg.norm(s2["y"] - y64) / torch.linalg.norm(y64))
                     rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))

@@ -104,6 +104,11 @@ typedef struct {
                              the returned iterate                                */
   double t_total;         /* seconds, wall clock of the solve                    */
   double t_pcg;           /* seconds spent in the Krylov solves (host clock)     */
+  double dual_inf;        /* dual infeasibility of the returned iterate (reported,
+                             not a stopping test; Sec. 6.1):
+                             max(||J1 (y - yhat) + D^T lambda + mu_y||_inf,
+                                 ||gamma J1 u + ctrl_sign lambda + mu_u||_inf)
+                             with lambda = psi p, mu_y = w_y, mu_u = e_u w_u     */
 } fde_admm_stats;
 
 /* Check a problem/parameter pair without touching the GPU.  FDE_OK or

@@ -567,6 +567,11 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
         HIP_TRY(fde::launch_objective(c->N, c->nx * c->ny, c->wts, q.gamma, R->f.y, R->f.yhat, R->f.u, c->part_pq,
                                       c->stream, &nb));
         HIP_TRY(fde::launch_pcg_scalar(fde::FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
+        // dual infeasibility (Sec. 6.1 reports it): B^T p = D^T lambda, lambda = psi p
+        HIP_TRY(xpass(c, R->f.p, c->fa, true, sti, -psi, nullptr));
+        HIP_TRY(ypass(c, R->f.p, c->fa, c->fw, true, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr));
+        HIP_TRY(fde::launch_dual_inf(R->k, R->f, q.gamma, c->fw, c->part_max, c->scal, c->stream));
         R->phase = PH_OBJ;
         return post_readback(c);
       }
@@ -575,6 +580,7 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
     }
     case PH_OBJ: {
       R->st.J = c->h_scal[fde::kDot];
+      R->st.dual_inf = c->h_scal[fde::kDual];
       R->st.t_total = now() - R->t0;
       R->st.t_pcg = R->t_pcg;
       R->phase = PH_DONE;

@@ -129,6 +129,7 @@ enum ScalarSlot {
   kD1,
   kD2,
   kD3,
+  kDual,      // dual infeasibility of the final ADMM iterate
   kNumScalars
 };
 enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kNumInts };
@@ -176,6 +177,10 @@ hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi,
 hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
                               int* nblocks);
 hipError_t launch_max3_finalize(const double* partial, int nblocks, double* scal, hipStream_t s);
+// dual infeasibility max(|J1 (y - yhat) + btp + e_y wy|, |gamma J1 u + k_u p + e_u wu|) over the
+// grid into scal[kDual]; btp = B^T p.  `partial` holds one slot per block.
+hipError_t launch_dual_inf(const AdmmConsts& k, const AdmmFields& f, double gamma, const double* btp,
+                           double* partial, double* scal, hipStream_t s);
 // up to four dot products (a[j], b[j]) in one pass; sums land in scal[kD0 + j]
 hipError_t launch_dots(int64_t n, int count, const double* const* a, const double* const* b, double* partial,
                        double* scal, hipStream_t s);

@@ -366,6 +366,36 @@ hipError_t launch_adjoint_rhs(int64_t n, int plane, const double* wts, const dou
   return hipGetLastError();
 }
 
+// dual infeasibility of the final iterate: block maxima, then one ordered max
+__global__ __launch_bounds__(kBlock) void k_dual_inf(AdmmConsts k, AdmmFields f, double gamma,
+                                                     const double* __restrict__ btp, double* partial) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < k.n; i += stride) {
+    const double j1 = k.wts[i / k.plane];
+    const double sy = j1 * (f.y[i] - f.yhat[i]) + btp[i] + k.e_y * f.wy[i];
+    const double su = gamma * j1 * f.u[i] + k.k_u * f.p[i] + k.e_u * f.wu[i];
+    m = nanmax(m, nanmax(fabs(sy), fabs(su)));
+  }
+  m = block_max<kBlock>(m);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_finalize(const double* partial, int nb, double* out) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) m = nanmax(m, partial[i]);
+  m = block_max<kBlock>(m);
+  if (threadIdx.x == 0) *out = m;
+}
+
+hipError_t launch_dual_inf(const AdmmConsts& k, const AdmmFields& f, double gamma, const double* btp,
+                           double* partial, double* scal, hipStream_t s) {
+  const int blocks = vec_blocks(k.n);
+  k_dual_inf<<<blocks, kBlock, 0, s>>>(k, f, gamma, btp, partial);
+  k_max_finalize<<<1, kBlock, 0, s>>>(partial, blocks, scal + kDual);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_objective(int64_t n, int plane, const double* wts, double gamma,
                                                       const double* y, const double* yhat, const double* u,
                                                       double* partial) {

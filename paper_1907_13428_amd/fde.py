@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("admm_iters", ctypes.c_int32), ("pcg_total", ctypes.c_int32), ("pcg_last", ctypes.c_int32),
                 ("pcg_max", ctypes.c_int32), ("r_p", ctypes.c_double), ("r_y", ctypes.c_double),
                 ("r_u", ctypes.c_double), ("J", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("t_pcg", ctypes.c_double)]
+                ("t_pcg", ctypes.c_double), ("dual_inf", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

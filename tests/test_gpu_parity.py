@@ -212,6 +212,14 @@ def _admm_compare(w, fp32=0, tol=1e-7):
     for k in ("y", "u", "zy", "zu", "p", "wy", "wu"):
         r = rel(got[k], getattr(ref, k))
         assert r <= tol, (k, r)
+    # objective and dual infeasibility of the returned iterate (the oracle's
+    # definitions evaluated on the GPU iterate)
+    sc = admm.scalars(w, op.disc_from(w))
+    J = kkt.objective(w, got["y"], got["u"])
+    assert abs(stats["J"] - J) <= 1e-12 * max(1.0, abs(J)), (stats["J"], J)
+    di = kkt.kkt_residuals(w, got["y"], got["u"], sc.psi * got["p"], sc.e_y * got["wy"],
+                           sc.e_u * got["wu"])["dual_inf"]
+    assert abs(stats["dual_inf"] - di) <= 1e-10 + 1e-8 * di, (stats["dual_inf"], di)
     return got, stats, ref
 
 
