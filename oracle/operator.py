@@ -215,3 +215,26 @@ def sampled_D(d: Disc, v, points):
         prev = v[t - 1, j, i] if t > 0 else 0.0
         out[n] = (v[t, j, i] - prev) / d.ht - lx - ly
     return out
+
+
+def sampled_DT(d: Disc, v, points):
+    """(D^T v) at the listed (t, j, i) points only, from row (t, j, i) of D^T
+    (column of D): its x-line, its y-line and its later time neighbour.
+    (L^T v)_i = c h^-a sum_k (G[k, i] d+_k + G[i, k] d-_k) v_k."""
+    ga = weights(d.alpha, d.nx)
+    gb = weights(d.beta, d.ny)
+    sx = riesz_factor(d.alpha) / d.hx ** d.alpha
+    sy = riesz_factor(d.beta) / d.hy ** d.beta
+    out = np.empty(len(points))
+    for n, (t, j, i) in enumerate(points):
+        k = np.arange(d.nx)
+        colG = np.where(k - i + 1 >= 0, ga[np.clip(k - i + 1, 0, d.nx)], 0.0)  # G[k, i]
+        rowG = np.where(i - k + 1 >= 0, ga[np.clip(i - k + 1, 0, d.nx)], 0.0)  # G[i, k]
+        lx = sx * np.sum((colG * d.dplus[j, :] + rowG * d.dminus[j, :]) * v[t, j, :])
+        k = np.arange(d.ny)
+        colG = np.where(k - j + 1 >= 0, gb[np.clip(k - j + 1, 0, d.ny)], 0.0)
+        rowG = np.where(j - k + 1 >= 0, gb[np.clip(j - k + 1, 0, d.ny)], 0.0)
+        ly = sy * np.sum((colG * d.dplus[:, i] + rowG * d.dminus[:, i]) * v[t, :, i])
+        nxt = v[t + 1, j, i] if t + 1 < d.nt else 0.0
+        out[n] = (v[t, j, i] - nxt) / d.ht - lx - ly
+    return out

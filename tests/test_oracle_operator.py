@@ -95,6 +95,20 @@ def test_sampled_rows_match_apply():
 
 
 @pytest.mark.parametrize("var", [False, True])
+def test_sampled_rows_match_assembled_matrix(var):
+    """Rows of D and of D^T at single points (used for the full-size GPU
+    checks) against the dense Kronecker assembly of eq. (4.9)."""
+    w = tiny(nx=9, ny=8, nt=3, var=var)
+    d = op.disc_from(w)
+    v = W.random_field(w.shape, 6)
+    D = op.assemble_D(d)
+    pts = [(0, 0, 0), (2, 7, 8), (1, 3, 4), (2, 0, 8), (0, 7, 0), (1, 1, 7)]
+    idx = [(t * w.ny + j) * w.nx + i for t, j, i in pts]
+    np.testing.assert_allclose(op.sampled_D(d, v, pts), (D @ v.ravel())[idx], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(op.sampled_DT(d, v, pts), (D.T @ v.ravel())[idx], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("var", [False, True])
 def test_m_matrix_and_positive_symmetric_part(var):
     w = tiny(var=var)
     d = op.disc_from(w)
