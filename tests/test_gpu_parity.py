@@ -201,7 +201,7 @@ def test_krylov_maxit_reports_not_converged():
 def _admm_compare(w, fp32=0, tol=1e-7):
     prob, prm = fde.from_workload(w, precond_fp32=fp32)
     with fde.Context(prob, prm) as ctx:
-        state, stats, status = ctx.admm_solve(dev(w.yhat))
+        state, stats, status = ctx.admm_solve(dev(w.yhat), g=None if w.g is None else dev(w.g))
         got = {k: host(v) for k, v in state.items()}
     K = stats["admm_iters"]
     ref = admm.admm_solve(w)
@@ -230,6 +230,77 @@ def test_admm_small(kind):
     got, stats, ref = _admm_compare(w)
     pol = kkt.polish(w, got["zy"], got["zu"])
     assert pol["ok"]
+
+
+def edge_case(kind):
+    if kind == "g_nonzero":
+        return W.small_mixed(nx=12, ny=8, nt=6).replace(g=0.5 * W.random_field((6, 8, 12), 31))
+    if kind == "free_control":
+        return W.small_state(nx=12, ny=8, nt=6).replace(ua=-np.inf, ub=np.inf)
+    if kind == "orders_near_1":
+        return W.small_mixed(nx=12, ny=8, nt=6).replace(alpha=1.05, beta=1.1)
+    raise KeyError(kind)
+
+
+@pytest.mark.parametrize("kind", ["g_nonzero", "free_control", "orders_near_1"])
+def test_admm_edge_cases(kind):
+    """A nonzero FDE right-hand side g, an unbounded control (only the state
+    bound active), and orders near 1 where the Riesz factor -1/(2 cos(a pi/2))
+    is large."""
+    banner("admm edge case", kind)
+    w = edge_case(kind)
+    got, stats, ref = _admm_compare(w)
+    assert kkt.polish(w, got["zy"], got["zu"])["ok"]
+
+
+def _admm_fixed(w, iters, tol=1e-7):
+    prob, prm = fde.from_workload(w, admm_tol=0.0, admm_maxit=iters)
+    with fde.Context(prob, prm) as ctx:
+        state, stats, status = ctx.admm_solve(dev(w.yhat))
+        got = {k: host(v) for k, v in state.items()}
+    assert stats["admm_iters"] == iters
+    ref = admm.admm_solve(w, iters=iters)
+    for k in ("y", "u", "zy", "zu", "p", "wy", "wu"):
+        r = rel(got[k], getattr(ref, k))
+        assert r <= tol, (k, r)
+    return got
+
+
+def test_admm_psi_scaling_of_B_only():
+    """psi_scaling = 2 (B = psi D, copies of u unscaled): 60 iterations."""
+    banner("admm psi_scaling 2")
+    _admm_fixed(W.small_mixed(nx=12, ny=8, nt=6).replace(psi_scaling=2), 60)
+
+
+def test_operators_without_psi_scaling():
+    banner("operators psi_scaling 0")
+    w = var_fields(W.small(nx=24, ny=12, nt=6)).replace(psi_scaling=0)
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    assert sc.psi == 1.0
+    v = W.random_field(w.shape, 33)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        y = zeros(w.shape)
+        ctx.apply_S(dev(v), y)
+        assert rel(host(y), admm.apply_S(d, sc, v)) <= 1e-11
+        ctx.precond(dev(v), y)
+        assert rel(host(y), pc.apply_precond(pc.precond_tables(w, d), v)) <= 1e-11
+
+
+def test_admm_paper_control_sign_exact_zero_optimum():
+    """The headline shape with the paper's control sign (D y + u = g): D is an
+    M-matrix, so u >= 0 forces y <= 0 <= yhat and the optimum is y = u = 0
+    exactly.  200 iterations against the oracle, then a converged solve."""
+    banner("admm ctrl_sign +1 zero optimum")
+    w = W.headline(nx=12, ny=12, nt=6).replace(ctrl_sign=1.0)
+    _admm_fixed(w, 200)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        state, stats, status = ctx.admm_solve(dev(w.yhat))
+        y, u = host(state["y"]), host(state["u"])
+    assert status == fde.FDE_OK
+    assert np.abs(y).max() <= 1e-5 and np.abs(u).max() <= 1e-5, (np.abs(y).max(), np.abs(u).max())
 
 
 def test_admm_headline_shape_small():
