@@ -182,7 +182,13 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
         b = Ry - apply_BT(d, sc, r / Mp)
         # 2. normal equations (3.9)
         if solver == "pcg":
-            y, it, _, _ = pcg(A, M, b, y, ktol, w.krylov_maxit)
+            if getattr(w, "tol_mode", 0) == 1:
+                # Sec. 6.1: 0.05 max{min of the previous iteration's three
+                # residuals, 1e-4}; before the first iteration the minimum is 0
+                prev = 0.0 if j == 1 else min(r_p, r_y, r_u)
+                ktol = 0.05 * max(prev, 1e-4)
+            x0 = np.zeros(shape) if getattr(w, "pcg_cold_start", 0) else y
+            y, it, _, _ = pcg(A, M, b, x0, ktol, w.krylov_maxit)
             pcg_counts.append(it)
         else:
             Lc = Schol

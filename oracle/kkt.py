@@ -28,6 +28,18 @@ def objective(w, y, u) -> float:
     return 0.5 * float(np.sum(J1 * e * e)) + 0.5 * w.gamma * float(np.sum(J1 * u * u))
 
 
+def el2_misfit(w, y) -> float:
+    """The paper's discrete L2 misfit between state and desired state
+    (Sec. 6.1): the trapezoidal rule in time (weight 1/2 on the last time
+    level, the initial level being zero) and the rectangle rule in space,
+    sqrt(h_x h_y h_t sum_k w_k sum_ij (y - yhat)^2)."""
+    d = op.disc_from(w)
+    wk = np.ones(w.nt)
+    wk[-1] = 0.5
+    e2 = np.sum((y - w.yhat) ** 2, axis=(1, 2))
+    return float(np.sqrt(d.hx * d.hy * d.ht * np.sum(wk * e2)))
+
+
 def multipliers(res):
     """Unscaled multipliers from ADMM iterates: lambda = psi p, mu_y = e_y w_y,
     mu_u = e_u w_u (e_y = 1; e_u = psi when the u copies are scaled)."""

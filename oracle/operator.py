@@ -1,8 +1,11 @@
 """The discretised fractional-diffusion constraint matrix D -- oracle, test infrastructure.
 
 Sec. 4: D = C_t (x) I - I (x) (L_x (+) L_y), eq. (4.9), with
-  * time: implicit Euler, i.e. the Grünwald matrix of eq. (4.5) at order 1:
-    C_t = (I - Z) / h_t with Z the sub-diagonal shift and y(t=0) = 0;
+  * time: the non-shifted Grünwald (Caputo) matrix of eq. (4.5) of order
+    alpha_t in (0, 1]: lower-triangular Toeplitz with first column
+    g_k(alpha_t) / h_t^alpha_t; at alpha_t = 1 the weights are (1, -1, 0, ...)
+    and C_t = (I - Z) / h_t is implicit Euler (Z the sub-diagonal shift);
+    y(t=0) = 0;
   * space: the shifted (p = 1) Grünwald matrix of eq. (4.6),
     G[i, j] = g_{i-j+1} for i-j+1 >= 0, and the two-sided operator
     L_a = (c_a / h^a) (diag(d+) G + diag(d-) G^T), c_a the Riesz factor of
@@ -35,6 +38,7 @@ class Disc:
     beta: float
     dplus: np.ndarray  # (ny, nx)
     dminus: np.ndarray  # (ny, nx)
+    alpha_t: float = 1.0  # order of the time derivative
 
 
 def disc_from(w) -> Disc:
@@ -43,7 +47,8 @@ def disc_from(w) -> Disc:
     dp = ones if w.dplus is None else np.asarray(w.dplus, dtype=np.float64)
     dm = ones if w.dminus is None else np.asarray(w.dminus, dtype=np.float64)
     return Disc(nx=w.nx, ny=w.ny, nt=w.nt, hx=1.0 / (w.nx + 1), hy=1.0 / (w.ny + 1),
-                ht=w.T / w.nt, alpha=w.alpha, beta=w.beta, dplus=dp, dminus=dm)
+                ht=w.T / w.nt, alpha=w.alpha, beta=w.beta, dplus=dp, dminus=dm,
+                alpha_t=getattr(w, "alpha_t", 1.0))
 
 
 def shifted_grunwald(a: float, n: int, g: np.ndarray | None = None) -> np.ndarray:
@@ -58,22 +63,33 @@ def shifted_grunwald(a: float, n: int, g: np.ndarray | None = None) -> np.ndarra
     return np.where(k >= 0, g[np.clip(k, 0, n)], 0.0)
 
 
-def time_matrix(nt: int, ht: float) -> np.ndarray:
-    """Implicit Euler: (I - Z) / h_t (eq. (4.5) at order 1: g = (1, -1, 0, ...))."""
-    return (np.eye(nt) - np.eye(nt, k=-1)) / ht
+def time_matrix(nt: int, ht: float, alpha_t: float = 1.0) -> np.ndarray:
+    """The Caputo matrix of eq. (4.5): entry (k, m) is g_{k-m}(alpha_t) / h_t^alpha_t
+    for k >= m.  Order 1 is implicit Euler, (I - Z) / h_t."""
+    if alpha_t == 1.0:
+        return (np.eye(nt) - np.eye(nt, k=-1)) / ht
+    g = weights(alpha_t, nt - 1)
+    k = np.arange(nt)[:, None] - np.arange(nt)[None, :]
+    return np.where(k >= 0, g[np.clip(k, 0, nt - 1)], 0.0) / ht ** alpha_t
 
 
 # --- line-wise applies -------------------------------------------------------
 def apply_E(d: Disc, v):
-    out = v.copy()
-    out[1:] -= v[:-1]
-    return out / d.ht
+    """C_t along every t-line: implicit Euler as a difference, a fractional
+    order as the dense lower-triangular product."""
+    if d.alpha_t == 1.0:
+        out = v.copy()
+        out[1:] -= v[:-1]
+        return out / d.ht
+    return np.tensordot(time_matrix(d.nt, d.ht, d.alpha_t), v, axes=([1], [0]))
 
 
 def apply_ET(d: Disc, v):
-    out = v.copy()
-    out[:-1] -= v[1:]
-    return out / d.ht
+    if d.alpha_t == 1.0:
+        out = v.copy()
+        out[:-1] -= v[1:]
+        return out / d.ht
+    return np.tensordot(time_matrix(d.nt, d.ht, d.alpha_t).T, v, axes=([1], [0]))
 
 
 def apply_Lx(d: Disc, v, transpose=False):
@@ -124,7 +140,7 @@ def assemble_D(d: Disc) -> np.ndarray:
         Li = line_matrix(d.beta, d.hy, ny, d.dplus[:, i], d.dminus[:, i])
         idx = np.arange(ny) * nx + i
         Ly[np.ix_(idx, idx)] = Li
-    return np.kron(time_matrix(nt, d.ht), np.eye(M)) - np.kron(np.eye(nt), Lx + Ly)
+    return np.kron(time_matrix(nt, d.ht, d.alpha_t), np.eye(M)) - np.kron(np.eye(nt), Lx + Ly)
 
 
 def assemble_D_sparse(d: Disc):
@@ -145,15 +161,17 @@ def assemble_D_sparse(d: Disc):
         vals.append(Li[jj, kk])
     Ly = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                        shape=(M, M))
-    Ct = sp.csr_matrix(time_matrix(nt, d.ht))
+    Ct = sp.csr_matrix(time_matrix(nt, d.ht, d.alpha_t))
     return (sp.kron(Ct, sp.identity(M)) - sp.kron(sp.identity(nt), Lx + Ly)).tocsr()
 
 
 class DSolver:
-    """Direct solves with D and D^T by time stepping (D is block lower
-    bidiagonal: diagonal blocks A = I/h_t - (L_x (+) L_y), sub-diagonal
-    -I/h_t), with one dense LU of the 2-D block A.  Right-hand sides are
-    (N,) or (N, m) arrays in the (t*ny + j)*nx + i ordering."""
+    """Direct solves with D and D^T by time stepping: D is block lower
+    triangular with blocks c_{k-m} I below the diagonal (c the first column of
+    the time matrix; block lower bidiagonal for implicit Euler) and diagonal
+    blocks A = c_0 I - (L_x (+) L_y).  One dense LU of the 2-D block A; step k
+    moves the history sum to the right-hand side.  Right-hand sides are (N,)
+    or (N, m) arrays in the (t*ny + j)*nx + i ordering."""
 
     def __init__(self, d: Disc):
         import scipy.linalg as sla
@@ -168,7 +186,8 @@ class DSolver:
         for i in range(d.nx):
             idx = np.arange(d.ny) * d.nx + i
             Ly[np.ix_(idx, idx)] = line_matrix(d.beta, d.hy, d.ny, d.dplus[:, i], d.dminus[:, i])
-        A = np.eye(M) / d.ht - Lx - Ly
+        self.c = time_matrix(d.nt, d.ht, d.alpha_t)[:, 0].copy()
+        A = self.c[0] * np.eye(M) - Lx - Ly
         self.lu = sla.lu_factor(A)
         self.M = M
 
@@ -180,27 +199,31 @@ class DSolver:
         shp = f.shape
         F = f.reshape(d.nt, M, -1)
         X = np.empty_like(F)
-        order = range(d.nt - 1, -1, -1) if trans else range(d.nt)
-        prev = None
-        for k in order:
-            rhs = F[k] if prev is None else F[k] + prev / d.ht
-            X[k] = sla.lu_solve(self.lu, rhs, trans=1 if trans else 0)
-            prev = X[k]
+        c = self.c
+        if not trans:
+            for k in range(d.nt):
+                rhs = F[k] - sum(c[k - m] * X[m] for m in range(k) if c[k - m] != 0.0)
+                X[k] = sla.lu_solve(self.lu, rhs)
+        else:
+            for k in range(d.nt - 1, -1, -1):
+                rhs = F[k] - sum(c[m - k] * X[m] for m in range(k + 1, d.nt) if c[m - k] != 0.0)
+                X[k] = sla.lu_solve(self.lu, rhs, trans=1)
         return X.reshape(shp)
 
 
 def psi_scale(d: Disc) -> float:
-    """psi = min{h_t, h_x^alpha, h_y^beta} (Sec. 5, time order 1)."""
-    return min(d.ht, d.hx ** d.alpha, d.hy ** d.beta)
+    """psi = min{h_t^alpha_t, h_x^alpha, h_y^beta} (Sec. 5)."""
+    return min(d.ht ** d.alpha_t, d.hx ** d.alpha, d.hy ** d.beta)
 
 
 def sampled_D(d: Disc, v, points):
     """(D v) at the listed (t, j, i) points only, from the point's own row of D:
-    its x-line, its y-line and its time neighbour.  Cost O(nx + ny) per point."""
+    its x-line, its y-line and its time history.  Cost O(nx + ny + nt) per point."""
     ga = weights(d.alpha, d.nx)
     gb = weights(d.beta, d.ny)
     sx = riesz_factor(d.alpha) / d.hx ** d.alpha
     sy = riesz_factor(d.beta) / d.hy ** d.beta
+    ct = time_matrix(d.nt, d.ht, d.alpha_t)[:, 0]
     out = np.empty(len(points))
     for n, (t, j, i) in enumerate(points):
         # row i of G: entries g_{i-k+1} for k <= i+1 ; row i of G^T: g_{k-i+1} for k >= i-1
@@ -212,19 +235,19 @@ def sampled_D(d: Disc, v, points):
         rowG = np.where(j - k + 1 >= 0, gb[np.clip(j - k + 1, 0, d.ny)], 0.0)
         rowGT = np.where(k - j + 1 >= 0, gb[np.clip(k - j + 1, 0, d.ny)], 0.0)
         ly = sy * (d.dplus[j, i] * rowG @ v[t, :, i] + d.dminus[j, i] * rowGT @ v[t, :, i])
-        prev = v[t - 1, j, i] if t > 0 else 0.0
-        out[n] = (v[t, j, i] - prev) / d.ht - lx - ly
+        out[n] = float(np.dot(ct[:t + 1], v[t::-1, j, i])) - lx - ly
     return out
 
 
 def sampled_DT(d: Disc, v, points):
     """(D^T v) at the listed (t, j, i) points only, from row (t, j, i) of D^T
-    (column of D): its x-line, its y-line and its later time neighbour.
+    (column of D): its x-line, its y-line and its later times.
     (L^T v)_i = c h^-a sum_k (G[k, i] d+_k + G[i, k] d-_k) v_k."""
     ga = weights(d.alpha, d.nx)
     gb = weights(d.beta, d.ny)
     sx = riesz_factor(d.alpha) / d.hx ** d.alpha
     sy = riesz_factor(d.beta) / d.hy ** d.beta
+    ct = time_matrix(d.nt, d.ht, d.alpha_t)[:, 0]
     out = np.empty(len(points))
     for n, (t, j, i) in enumerate(points):
         k = np.arange(d.nx)
@@ -235,6 +258,5 @@ def sampled_DT(d: Disc, v, points):
         colG = np.where(k - j + 1 >= 0, gb[np.clip(k - j + 1, 0, d.ny)], 0.0)
         rowG = np.where(j - k + 1 >= 0, gb[np.clip(j - k + 1, 0, d.ny)], 0.0)
         ly = sy * np.sum((colG * d.dplus[:, i] + rowG * d.dminus[:, i]) * v[t, :, i])
-        nxt = v[t + 1, j, i] if t + 1 < d.nt else 0.0
-        out[n] = (v[t, j, i] - nxt) / d.ht - lx - ly
+        out[n] = float(np.dot(ct[:d.nt - t], v[t:, j, i])) - lx - ly
     return out

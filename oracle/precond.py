@@ -68,7 +68,7 @@ def precond_tables(w, d: Disc):
     dbm = float(np.mean(d.dminus))
     Lx = mean_line_operator(d.alpha, d.hx, d.nx, dbp, dbm)
     Ly = mean_line_operator(d.beta, d.hy, d.ny, dbp, dbm)
-    Ct = time_matrix(d.nt, d.ht)
+    Ct = time_matrix(d.nt, d.ht, d.alpha_t)
     col_x, col_y, col_t = tchan_column(Lx), tchan_column(Ly), tchan_column(Ct)
     lam_x = dft_eigenvalues(col_x)
     lam_y = dft_eigenvalues(col_y)

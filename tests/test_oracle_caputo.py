@@ -1,0 +1,158 @@
+"""Pins for the fractional-in-time (Caputo) pieces of the oracle: the time
+matrix of eq. (4.5), its use in D (eq. (4.9)), the time T. Chan table, the
+dynamic Krylov tolerance and the L2 misfit of Sec. 6.1."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special as ss
+
+import workloads as W
+from oracle import admm, kkt, precond
+from oracle import operator as op
+from oracle.grunwald import weights
+
+
+@pytest.mark.parametrize("a", [0.1, 0.3, 0.7, 0.9])
+def test_time_weights_binomial_form_and_signs(a):
+    """g_k = (-1)^k binom(a, k) = Gamma(k - a) / (Gamma(-a) Gamma(k + 1)), and
+    Prop. 4.1 for 0 < a < 1: g_0 > 0, g_k < 0 (k >= 1), every partial sum > 0."""
+    n = 200
+    g = weights(a, n)
+    k = np.arange(n + 1)
+    ref = (-1.0) ** k * ss.binom(a, k)
+    np.testing.assert_allclose(g, ref, rtol=1e-12, atol=1e-300)
+    assert g[0] > 0 and np.all(g[1:] < 0)
+    assert np.all(np.cumsum(g) > 0)
+
+
+def test_order_one_is_implicit_euler_exactly():
+    nt, ht = 9, 0.1
+    g = weights(1.0, nt - 1)
+    assert np.array_equal(g[:3], [1.0, -1.0, 0.0]) and np.all(g[2:] == 0.0)
+    kk = np.arange(nt)[:, None] - np.arange(nt)[None, :]
+    general = np.where(kk >= 0, g[np.clip(kk, 0, nt - 1)], 0.0) / ht
+    assert np.array_equal(general, op.time_matrix(nt, ht, 1.0))
+
+
+@pytest.mark.parametrize("a", [0.3, 0.7])
+@pytest.mark.parametrize("p", [1, 2])
+def test_caputo_matrix_first_order_convergence(a, p):
+    """The Grünwald sum of eq. (4.5) applied to y = t^p (y(0) = 0) converges at
+    first order to the Caputo derivative Gamma(p+1)/Gamma(p+1-a) t^(p-a),
+    compared on t in [0.5, 1]."""
+    errs = []
+    for n in (200, 400, 800):
+        h = 1.0 / n
+        t = h * np.arange(1, n + 1)
+        Dy = op.time_matrix(n, h, a) @ t ** p
+        exact = math.gamma(p + 1) / math.gamma(p + 1 - a) * t ** (p - a)
+        sel = t >= 0.5
+        errs.append(np.max(np.abs(Dy - exact)[sel]))
+    r1, r2 = errs[1] / errs[0], errs[2] / errs[1]
+    assert 0.4 < r1 < 0.6 and 0.4 < r2 < 0.6, errs
+
+
+def caputo_case(var=True, nx=9, ny=8, nt=5, a_t=0.7):
+    w = W.small(nx=nx, ny=ny, nt=nt).replace(alpha=1.3, beta=1.7, alpha_t=a_t, T=0.8)
+    if var:
+        w.dplus = W.coef_sine_x(nx, ny)
+        rng = np.random.Generator(np.random.PCG64(3))
+        w.dminus = 1.0 + 0.3 * rng.uniform(size=(ny, nx))
+    return w
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_caputo_D_apply_rows_and_solver_match_assembly(var):
+    w = caputo_case(var)
+    d = op.disc_from(w)
+    assert d.alpha_t == 0.7
+    D = op.assemble_D(d)
+    v = W.random_field(w.shape, 8)
+    np.testing.assert_allclose(op.apply_D(d, v).ravel(), D @ v.ravel(), rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(op.apply_DT(d, v).ravel(), D.T @ v.ravel(), rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(op.assemble_D_sparse(d).toarray(), D, rtol=1e-14, atol=1e-12)
+    pts = [(0, 0, 0), (4, 7, 8), (2, 3, 4), (4, 0, 8), (0, 7, 0), (3, 1, 7)]
+    idx = [(t * w.ny + j) * w.nx + i for t, j, i in pts]
+    np.testing.assert_allclose(op.sampled_D(d, v, pts), (D @ v.ravel())[idx], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(op.sampled_DT(d, v, pts), (D.T @ v.ravel())[idx], rtol=1e-12, atol=1e-12)
+    S = op.DSolver(d)
+    f = W.random_field(w.shape, 9).ravel()
+    np.testing.assert_allclose(D @ S.solve(f), f, rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(D.T @ S.solve(f, trans=True), f, rtol=1e-10, atol=1e-10)
+
+
+def test_caputo_D_is_an_m_matrix():
+    w = caputo_case(var=True, nx=6, ny=5, nt=4)
+    D = op.assemble_D(op.disc_from(w))
+    off = D - np.diag(np.diag(D))
+    assert np.all(np.diag(D) > 0) and np.all(off <= 1e-15)
+    assert np.all(np.linalg.inv(D) >= -1e-12)
+
+
+def test_time_tchan_is_the_frobenius_projection():
+    """T. Chan column of the Caputo matrix = the circulant nearest in the
+    Frobenius norm (least squares over circulants, computed directly)."""
+    nt, ht, a = 7, 0.1, 0.6
+    C = op.time_matrix(nt, ht, a)
+    c = precond.tchan_column(C)
+    # brute force: circulant basis P^k, least squares in the Frobenius norm
+    P = np.roll(np.eye(nt), 1, axis=0)
+    basis = [np.linalg.matrix_power(P, k) for k in range(nt)]
+    A = np.stack([b.ravel() for b in basis], axis=1)
+    coef, *_ = np.linalg.lstsq(A, C.ravel(), rcond=None)
+    np.testing.assert_allclose(c, coef, rtol=1e-12, atol=1e-12)
+
+
+def test_psi_uses_the_time_order():
+    w = caputo_case()
+    d = op.disc_from(w)
+    assert op.psi_scale(d) == min(d.ht ** 0.7, d.hx ** 1.3, d.hy ** 1.7)
+
+
+def test_dynamic_tolerance_reaches_the_polished_optimum():
+    """The paper's test problem at 8^3 with its dynamic Krylov tolerance (never
+    below 5e-6) and its ADMM tolerance 1e-4: the z-iterates polish (KKT on the
+    active set) to the exact optimum, which the iterate approximates to the
+    accuracy that tolerance allows."""
+    w = W.paper_test(8, delta=2.0)
+    r = admm.admm_solve(w)
+    assert r.converged and max(r.r_p, r.r_y, r.r_u) <= 1e-4
+    pol = kkt.polish(w, r.zy, r.zu)
+    assert pol["ok"]
+    assert kkt.rel(r.y, pol["y"]) < 1e-3
+
+
+def table5():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_table5.json")) as f:
+        rec = json.load(f)
+    return [dict(zip(rec["columns"], row)) for row in rec["rows"]]
+
+
+def test_paper_table5_smallest_grid():
+    """The smallest row of the paper's Table 5 (tests/golden/paper_table5.json:
+    8^3, delta = 2; box on both variables, orders 0.7 / 1.3, gamma 1e-4): the
+    oracle, with PCG started from zero as MATLAB's pcg does by default, gives
+    the printed dual infeasibility to 1%, the printed PCG average to 10% and
+    the printed ADMM count to 5%."""
+    row = table5()[0]
+    w = W.paper_test(row["n"], delta=row["delta"])
+    r = admm.admm_solve(w)
+    assert r.converged
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    di = kkt.kkt_residuals(w, r.y, r.u, sc.psi * r.p, r.wy, sc.e_u * r.wu)["dual_inf"]
+    assert abs(di - row["dual_inf"]) <= 0.01 * row["dual_inf"], di
+    assert abs(np.mean(r.pcg_iters) - row["pcg_avg"]) <= 0.1 * row["pcg_avg"], np.mean(r.pcg_iters)
+    assert abs(r.iters - row["admm_iters"]) <= 0.05 * row["admm_iters"], r.iters
+
+
+def test_el2_misfit_closed_form():
+    """y = yhat + c: E = |c| sqrt(h_x h_y h_t n_x n_y (n_t - 1/2))."""
+    w = W.paper_test(8)
+    d = op.disc_from(w)
+    c = 0.3
+    e = kkt.el2_misfit(w, w.yhat + c)
+    assert abs(e - c * math.sqrt(d.hx * d.hy * d.ht * w.nx * w.ny * (w.nt - 0.5))) < 1e-14

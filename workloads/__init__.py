@@ -52,6 +52,9 @@ class Workload:
     admm_maxit: int = 100000
     psi_scaling: int = 1  # 1: B and the u copies scaled by psi; 2: B only; 0: none
     obj_weights: int = 0  # 0: all ones, 1: trapezoidal in time (eq. 4.10)
+    alpha_t: float = 1.0  # order of the time derivative in (0, 1]; 1 = implicit Euler
+    tol_mode: int = 0  # 0: fixed Krylov tolerance; 1: the dynamic rule of Sec. 6.1
+    pcg_cold_start: int = 0  # 0: PCG starts from the previous y; 1: from zero
     yhat: Optional[np.ndarray] = None  # (nt, ny, nx)
     dplus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
     dminus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
@@ -214,6 +217,23 @@ def differentiation(nx=512, ny=512, nt=32, **kw) -> Workload:
     w = Workload(name=f"differentiation_{nx}x{ny}x{nt}", nx=nx, ny=ny, nt=nt, alpha=1.4,
                  beta=1.6, gamma=1e-4, ua=-1.0, ub=1.0)
     w.yhat = target_sinusoid_sum(nx, ny, nt, BASE_SEED + 3)
+    return w.replace(**kw)
+
+
+def paper_test(n=16, alpha_t=0.7, beta=1.3, gamma=1e-4, ya=-4.0, ua=-350.0, delta=2.0, **kw) -> Workload:
+    """The paper's test problem (Sec. 6.1): n x n x n grid on (0,1)^2 x (0,T],
+    h_t = h_x = 1/(n+1) (so T = n/(n+1)), Caputo time derivative of order
+    alpha_t, Riesz derivatives of order beta in both space directions with
+    constant coefficients, yhat = 10 cos(10 x1) sin(x1 x2)(1 - exp(-5t)),
+    trapezoidal objective weights, symmetric bounds y_b = -y_a and
+    u_b = -u_a, D y + u = 0, rho = 1.618, ADMM tolerance 1e-4, the dynamic
+    Krylov tolerance, and PCG started from zero in every x-step.  Table 5 of
+    the paper pairs n with delta."""
+    T = n / (n + 1.0)
+    w = Workload(name=f"paper_{n}^3", nx=n, ny=n, nt=n, alpha=beta, beta=beta, gamma=gamma,
+                 ua=ua, ub=-ua, ya=ya, yb=-ya, T=T, ctrl_sign=1.0, delta=delta, rho=1.618,
+                 admm_tol=1e-4, obj_weights=1, alpha_t=alpha_t, tol_mode=1, pcg_cold_start=1)
+    w.yhat = target_paper(n, n, n, T)
     return w.replace(**kw)
 
 
