@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--batch-cap", type=int, default=30, help="ADMM iterations per batched instance")
     ap.add_argument("--pass-reps", type=int, default=50, help="launches per pass for the per-pass timing")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's Table 5 protocol")
     return ap.parse_args()
 
 
@@ -128,6 +129,40 @@ def measured_traffic(pass_name, tile_width):
             or rec.get("source_sha256") != kernel_source_hash()):
         return None
     return rec.get("traffic_bytes")
+
+
+def paper_table5_leg(fde, torch):
+    """The paper's test problem and protocol (Sec. 6.1; Caputo order 0.7,
+    Riesz orders 1.3, box on both variables, dynamic Krylov tolerance, PCG from
+    zero, ADMM tolerance 1e-4) at the Table 5 grid sizes, FP64 on the GPU,
+    beside the printed figures (MATLAB on a CPU)."""
+    import workloads as W
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_table5.json")) as f:
+        rec = json.load(f)
+    rows = []
+    for row in (dict(zip(rec["columns"], r)) for r in rec["rows"]):
+        w = W.paper_test(row["n"], delta=row["delta"])
+        prob, prm = fde.from_workload(w)
+        yhat = torch.from_numpy(w.yhat).to("cuda")
+        with fde.Context(prob, prm) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            state, st, status = ctx.admm_solve(yhat)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            # discrete L2 misfit: trapezoidal in time (1/2 on the last level), sum in space
+            h = 1.0 / (row["n"] + 1)
+            e2 = ((state["y"] - yhat) ** 2).sum(dim=(1, 2))
+            e2[-1] *= 0.5
+            el2 = float(torch.sqrt(h * h * (w.T / w.nt) * e2.sum()))
+        rows.append({"n": row["n"], "delta": row["delta"], "converged": status == 0,
+                     "admm_iters": st["admm_iters"], "paper_admm_iters": row["admm_iters"],
+                     "pcg_avg": round(st["pcg_total"] / max(st["admm_iters"], 1), 2),
+                     "paper_pcg_avg": row["pcg_avg"], "E_L2": round(el2, 4), "paper_E_L2": row["E_L2"],
+                     "dual_inf": st["dual_inf"], "paper_dual_inf": row["dual_inf"], "s": round(dt, 4),
+                     "paper_s": row["time_s"]})
+    return {"rows": rows, "paper_times": rec["time_note"]}
 
 
 def batched_leg(fde, torch, cap):
@@ -233,6 +268,11 @@ def main():
                     rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))
                 out[tag] = rec
         out["admm_solve_s"] = out["fp64"]["admm_solve_s"]
+
+    # ---- the paper's own test problem and protocol (Table 5 sizes) -----------
+    if not a.no_paper:
+        progress("paper test problem, Table 5 sizes")
+        out["paper_table5"] = paper_table5_leg(fde, torch)
 
     # ---- batched form: 64 uneven instances, concurrent vs sequential ---------
     if not a.no_batch:

@@ -67,14 +67,20 @@ typedef struct {
                              NULL means d+ = 1.  Copied at create time.        */
   const double* dminus;   /* (host) same for d-                                 */
   double ctrl_sign;       /* s = +1: D y + u = g (eq. (4.8)); -1: D y - u = g    */
-  int32_t psi_scaling;    /* 1: scale the constraints by psi = min{ht, hx^alpha,
-                             hy^beta} and the copies of u by psi (Sec. 5, 6.1);
+  int32_t psi_scaling;    /* 1: scale the constraints by psi = min{ht^alpha_t,
+                             hx^alpha, hy^beta} and the copies of u by psi
+                             (Sec. 5, 6.1);
                              2: scale the FDE constraint only (u copies
                              unscaled); 0: unscaled                             */
   int32_t obj_weights;    /* 0: J1 = I; 1: trapezoidal, 1/2 on the last time
                              block (eq. (4.10))                                 */
   int32_t precond_fp32;   /* 1: run the circulant preconditioner in float32
                              (operator, residuals, dots, ADMM stay float64)     */
+  double alpha_t;         /* order of the Caputo time derivative, in (0, 1]:
+                             the non-shifted Grünwald matrix of eq. (4.5),
+                             (1/ht^alpha_t) lower-triangular Toeplitz of the
+                             weights g_k(alpha_t); 1 (and 0, read as 1) is
+                             implicit Euler.  psi then uses ht^alpha_t.        */
 } fde_problem;
 
 /* ADMM and Krylov settings (Algorithm 1; Sec. 6.1). */
@@ -90,6 +96,8 @@ typedef struct {
   double admm_tol;        /* stop when max of the three inf-norm residuals
                              <= admm_tol (0: run exactly admm_maxit iterations) */
   int32_t admm_maxit;     /* > 0                                                */
+  int32_t pcg_cold_start; /* 0: each x-step's PCG starts from the previous y;
+                             1: from zero (MATLAB pcg's default, Sec. 6.1)     */
 } fde_admm_params;
 
 typedef struct {

@@ -76,6 +76,8 @@ struct fde_ctx {
   double2 *twx_emb = nullptr, *twy_emb = nullptr;
   void *twx = nullptr, *twy = nullptr, *twt = nullptr;
   double2 *tcx = nullptr, *tcy = nullptr, *tct = nullptr;
+  double2 *ltA = nullptr, *ltTA = nullptr, *twt_emb = nullptr;  // fractional time: 2nt embedding
+  bool frac_t = false;
   double *dplus = nullptr, *dminus = nullptr;
   double *invMp = nullptr, *My = nullptr, *Mu = nullptr, *Mp = nullptr, *wts = nullptr, *ones = nullptr;
   double2 *dxA = nullptr, *dxB = nullptr, *dyA = nullptr, *dyB = nullptr;  // dL/dalpha, dL/dbeta
@@ -150,9 +152,11 @@ hipError_t upload_tw(fde_ctx* c, void** dst, const std::vector<cd>& src, bool fp
 }
 
 // maximum number of blocks any reducing launch uses (partial-sum capacity)
-int max_partials(int nx, int ny, int nt) {
+int max_partials(int nx, int ny, int nt, bool frac_t) {
   const long long N = (long long)nx * ny * nt;
   long long m = 2048;  // vector kernels
+  // t-pass: tiles of at least 2 columns of the nx*ny plane
+  if (frac_t) m = std::max(m, ((long long)nx * ny + 1) / 2);
   // y-pass: tiles * nt with at least 2 columns per tile
   m = std::max(m, (long long)((nx + 1) / 2) * nt);
   // x-inverse of the preconditioner: pairs of lines, at least one pair per block
@@ -212,16 +216,59 @@ hipError_t ypass(fde_ctx* c, const double* in, const double* acc, double* out, b
   return fde::launch_ypass(a, tr, c->var, c->stream, nb);
 }
 
+// t-pass of a fractional time order: out_t = osc[t] (acc + s C_t(^T) in) + esc[t] extra, the
+// t-lines of the field viewed as [nt][nx*ny] run through the y-pass kernel (rows = time levels)
+hipError_t tpass(fde_ctx* c, const double* in, const double* acc, double* out, bool tr, double s,
+                 const double* osc, const double* extra, const double* esc, const double* dotv,
+                 double* partial, const int* done, int* nb) {
+  fde::LinePassArgs a{};
+  a.nx = c->nx * c->ny;
+  a.ny = c->nt;
+  a.nt = 1;
+  a.in = in;
+  a.out = out;
+  a.acc = acc;
+  a.tw = c->twt_emb;
+  a.lamA = tr ? c->ltTA : c->ltA;
+  a.s_sp = s;
+  a.tile = 0;
+  a.row_scale = 1;
+  a.oscale = osc;
+  a.extra = extra;
+  a.escale = esc;
+  a.dotv = dotv;
+  a.partial = partial;
+  a.done = done;
+  return fde::launch_ypass(a, tr, false, c->stream, nb);
+}
+
+// out = osc[t] (scale D(^T) in) + esc[t] extra, with optional partial sums of (dotv, out);
+// tmp1 and tmp2 are workspace fields distinct from in and out.  Implicit Euler: the time
+// difference rides in the x-pass and the epilogue in the y-pass; a fractional time order
+// adds the t-pass, which then carries the epilogue.
+hipError_t apply_op(fde_ctx* c, const double* in, double* out, bool tr, double scale, double* tmp1, double* tmp2,
+                    const double* osc, const double* extra, const double* esc, const double* dotv, double* partial,
+                    const int* done, int* nb) {
+  hipError_t e;
+  if (!c->frac_t) {
+    if ((e = xpass(c, in, tmp1, tr, scale / c->su.ht, -scale, done)) != hipSuccess) return e;
+    return ypass(c, in, tmp1, out, tr, -scale, osc, extra, esc, dotv, partial, done, nb);
+  }
+  if ((e = xpass(c, in, tmp1, tr, 0.0, -scale, done)) != hipSuccess) return e;
+  if ((e = ypass(c, in, tmp1, tmp2, tr, -scale, nullptr, nullptr, nullptr, nullptr, nullptr, done, nullptr)) !=
+      hipSuccess)
+    return e;
+  return tpass(c, in, tmp2, out, tr, scale, osc, extra, esc, dotv, partial, done, nb);
+}
+
 // y = S x = M_y x + B^T M_p^{-1} B x, optional partial sums of (x, y)
 hipError_t apply_S(fde_ctx* c, const double* x, double* y, double* partial, const int* done, int* nb) {
-  const double psi = c->su.psi, sti = psi / c->su.ht;
+  const double psi = c->su.psi;
   hipError_t e;
-  if ((e = xpass(c, x, c->fa, false, sti, -psi, done)) != hipSuccess) return e;
-  if ((e = ypass(c, x, c->fa, c->fw, false, -psi, c->invMp, nullptr, nullptr, nullptr, nullptr, done,
-                 nullptr)) != hipSuccess)
+  if ((e = apply_op(c, x, c->fw, false, psi, c->fa, c->fb, c->invMp, nullptr, nullptr, nullptr, nullptr, done,
+                    nullptr)) != hipSuccess)
     return e;
-  if ((e = xpass(c, c->fw, c->fb, true, sti, -psi, done)) != hipSuccess) return e;
-  return ypass(c, c->fw, c->fb, y, true, -psi, nullptr, x, c->My, partial ? x : nullptr, partial, done, nb);
+  return apply_op(c, c->fw, y, true, psi, c->fa, c->fb, nullptr, x, c->My, partial ? x : nullptr, partial, done, nb);
 }
 
 fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
@@ -464,12 +511,13 @@ struct AdmmRun {
 fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   const auto& s = c->su;
   const fde_admm_params& q = c->prm;
-  const double psi = s.psi, sti = psi / s.ht;
+  const double psi = s.psi;
   // 1. b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
   HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
-  HIP_TRY(xpass(c, c->av, c->fb, true, sti, -psi, nullptr));
-  HIP_TRY(ypass(c, c->av, c->fb, c->bvec, true, -psi, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr, nullptr));
-  // 2. S y = b by PCG, warm-started from the previous y
+  HIP_TRY(apply_op(c, c->av, c->bvec, true, psi, c->fb, c->fa, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr,
+                   nullptr));
+  // 2. S y = b by PCG, warm-started from the previous y (or from zero)
+  if (q.pcg_cold_start) HIP_TRY(fde::launch_lincomb(c->N, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, R->f.y, c->stream));
   const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(R->prev_min, 1e-4) : q.krylov_tol;
   R->tp = now();
   R->phase = PH_PCG;
@@ -524,7 +572,7 @@ fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* 
 fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
   const auto& s = c->su;
   const fde_admm_params& q = c->prm;
-  const double psi = s.psi, sti = psi / s.ht;
+  const double psi = s.psi;
   switch (R->phase) {
     case PH_PCG: {
       if (!krylov_continue(c, &R->kr)) return FDE_OK;
@@ -539,9 +587,8 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
       R->st.pcg_last = it;
       if (it > R->st.pcg_max) R->st.pcg_max = it;
       // 3-5. By ; p, u recovery ; projection ; dual updates ; residual maxima
-      HIP_TRY(xpass(c, R->f.y, c->fa, false, sti, -psi, nullptr));
-      HIP_TRY(ypass(c, R->f.y, c->fa, c->By, false, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                    nullptr));
+      HIP_TRY(apply_op(c, R->f.y, c->By, false, psi, c->fa, c->fb, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr));
       int nb = 0;
       HIP_TRY(fde::launch_admm_update(R->k, R->f, psi, c->stream, &nb));
       HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
@@ -568,9 +615,8 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
                                       c->stream, &nb));
         HIP_TRY(fde::launch_pcg_scalar(fde::FIN_DOT, c->part_pq, nb, c->scal, c->ints, c->stream));
         // dual infeasibility (Sec. 6.1 reports it): B^T p = D^T lambda, lambda = psi p
-        HIP_TRY(xpass(c, R->f.p, c->fa, true, sti, -psi, nullptr));
-        HIP_TRY(ypass(c, R->f.p, c->fa, c->fw, true, -psi, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr));
+        HIP_TRY(apply_op(c, R->f.p, c->fw, true, psi, c->fa, c->fb, nullptr, nullptr, nullptr, nullptr, nullptr,
+                         nullptr, nullptr));
         HIP_TRY(fde::launch_dual_inf(R->k, R->f, q.gamma, c->fw, c->part_max, c->scal, c->stream));
         R->phase = PH_OBJ;
         return post_readback(c);
@@ -836,6 +882,12 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   chk(upload_c(c, &c->tcx, s.x.tchan));
   chk(upload_c(c, &c->tcy, s.y.tchan));
   chk(upload_c(c, &c->tct, s.tchan_t));
+  c->frac_t = s.frac_t;
+  if (s.frac_t) {
+    chk(upload_c(c, &c->ltA, s.lam_t));
+    chk(upload_c(c, &c->ltTA, s.lam_tT));
+    chk(upload_c(c, &c->twt_emb, s.tw_t_emb));
+  }
   chk(c->alloc(&c->invMp, c->nt));
   chk(c->alloc(&c->My, c->nt));
   chk(c->alloc(&c->Mu, c->nt));
@@ -857,7 +909,7 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
     chk(c->alloc(&sp, specn));
     c->spec = sp;
   }
-  c->maxpart = max_partials(c->nx, c->ny, c->nt);
+  c->maxpart = max_partials(c->nx, c->ny, c->nt, s.frac_t);
   chk(c->alloc(&c->part_pq, 2 * (size_t)c->maxpart));
   chk(c->alloc(&c->part_rr, (size_t)c->maxpart));
   chk(c->alloc(&c->part_rz, (size_t)c->maxpart));
@@ -960,9 +1012,8 @@ fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) 
   if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_A: null or aliased fields");
   CHECK_ALIGNED("fde_apply_A", x, y);
   const bool tr = transpose != 0;
-  const double sti = 1.0 / ctx->su.ht;
-  HIP_TRY(xpass(ctx, x, ctx->fa, tr, sti, -1.0, nullptr));
-  HIP_TRY(ypass(ctx, x, ctx->fa, y, tr, -1.0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+  HIP_TRY(apply_op(ctx, x, y, tr, 1.0, ctx->fa, ctx->fb, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   nullptr));
   return FDE_OK;
 }
 
@@ -1132,6 +1183,8 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   double* lam = lambda_out ? lambda_out : c->z;
   if (adjoint_solve) {
     if (!wy) return (fde_status)fail(FDE_EINVAL, "fde_grad: the adjoint solve needs wy");
+    if (c->frac_t)
+      return (fde_status)fail(FDE_EINVAL, "fde_grad: the adjoint solve steps implicit Euler time only (alpha_t = 1)");
     const fde_status st = adjoint_solve_impl(c, yhat, y, wy, lam);
     if (st < 0) return st;
     HIP_TRY(launch_grad_fields(c->N, c->nx * c->ny, c->wts, y, yhat, p, c->su.psi, dyhat, nullptr, c->stream));
@@ -1301,6 +1354,7 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
   using namespace fde;
   if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
   if (which < 0 || which > 8 || reps <= 0) return (fde_status)fail(FDE_EINVAL, "fde_time_pass: bad pass or reps");
+  if (ctx->frac_t) return (fde_status)fail(FDE_EINVAL, "fde_time_pass: the pass list is that of alpha_t = 1");
   fde_ctx* c = ctx;
   const size_t N = (size_t)c->N;
   const size_t sb = (size_t)c->H * c->ny * c->nt * (c->fp32 ? 8 : 16);

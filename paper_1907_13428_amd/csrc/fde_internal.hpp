@@ -34,6 +34,8 @@ __device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<do
 //   x-pass:  out = s_time * (E or E^T) in + s_sp * (L_x or L_x^T) in
 //   y-pass:  out_t = oscale[t] * (acc + s_sp * (L_y or L_y^T) in) + escale[t] * extra
 //            (+ optional partial sums of dotv * out)
+//   t-pass (fractional time order): the y-pass kernel on the field viewed as
+//            [nt][nx*ny] with the time-matrix tables, oscale/escale by row
 // E is the implicit-Euler time difference (v_t - v_{t-1}) / h_t, E^T uses
 // v_{t+1}.  The spatial operators are (c_a/h^a)(diag(d+) G + diag(d-) G^T)
 // applied by a 2n circulant embedding; the eigenvalue tables already carry
@@ -60,6 +62,8 @@ struct LinePassArgs {
   double* partial;       // one slot per block
   const int* done;       // early-exit flag (may be nullptr)
   int tile;              // y-pass tile variant (autotuned): 0 widest, 1 half, 2 quarter
+  int row_scale;         // y-pass kernel run along t (rows = time levels): oscale and
+                         // escale are indexed by the row, not the slice
 };
 
 // launchers (return hipError_t of the launch)

@@ -45,6 +45,7 @@ int validate_params(const fde_admm_params* q, std::string* msg) {
   }
   if (!(q->krylov_tol >= 0) || !finite(q->krylov_tol)) { *msg = "krylov_tol must be >= 0"; return FDE_EINVAL; }
   if (q->krylov_maxit <= 0) { *msg = "krylov_maxit must be > 0"; return FDE_EINVAL; }
+  if (q->pcg_cold_start != 0 && q->pcg_cold_start != 1) { *msg = "pcg_cold_start must be 0 or 1"; return FDE_EINVAL; }
   if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
   if (!(q->admm_tol >= 0) || !finite(q->admm_tol)) { *msg = "admm_tol must be >= 0"; return FDE_EINVAL; }
   if (q->admm_maxit <= 0) { *msg = "admm_maxit must be > 0"; return FDE_EINVAL; }
@@ -65,6 +66,10 @@ int validate(const fde_problem* p, const fde_admm_params* q, std::string* msg) {
   if (!(p->T > 0) || !finite(p->T)) { *msg = "T must be finite and > 0"; return FDE_EINVAL; }
   if (!(p->alpha > 1.0 && p->alpha <= 2.0)) { *msg = fmt("alpha=%g outside (1, 2]", p->alpha); return FDE_EINVAL; }
   if (!(p->beta > 1.0 && p->beta <= 2.0)) { *msg = fmt("beta=%g outside (1, 2]", p->beta); return FDE_EINVAL; }
+  if (!(p->alpha_t == 0.0 || (p->alpha_t > 0.0 && p->alpha_t <= 1.0))) {
+    *msg = fmt("alpha_t=%g outside (0, 1]", p->alpha_t);
+    return FDE_EINVAL;
+  }
   if (p->ctrl_sign != 1.0 && p->ctrl_sign != -1.0) { *msg = "ctrl_sign must be +1 or -1"; return FDE_EINVAL; }
   if (p->psi_scaling < 0 || p->psi_scaling > 2) { *msg = "psi_scaling must be 0, 1 or 2"; return FDE_EINVAL; }
   if (p->obj_weights != 0 && p->obj_weights != 1) { *msg = "obj_weights must be 0 or 1"; return FDE_EINVAL; }
@@ -265,14 +270,35 @@ int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::s
   s->dbar_minus = mean(s->dminus);
   build_axis(p->nx, hx, p->alpha, s->dbar_plus, s->dbar_minus, s->var, &s->x);
   build_axis(p->ny, hy, p->beta, s->dbar_plus, s->dbar_minus, s->var, &s->y);
-  // time: implicit Euler (I - Z)/ht; T. Chan column (1, -(nt-1)/nt, 0, ..)/ht
-  std::vector<double> tp(p->nt, 0.0), tn(p->nt, 0.0);
-  tp[0] = 1.0 / s->ht;
-  if (p->nt > 1) tp[1] = -1.0 / s->ht;
-  s->tchan_t = tchan_eigs(tp, tn);
+  // time: the Caputo matrix of eq. (4.5), lower-triangular Toeplitz with first
+  // column g_k(alpha_t) / ht^alpha_t; order 1 gives (1, -1, 0, ..)/ht, implicit Euler
+  s->alpha_t = (p->alpha_t == 0.0) ? 1.0 : p->alpha_t;
+  s->frac_t = s->alpha_t != 1.0;
+  const double hta = std::pow(s->ht, s->alpha_t);
+  {
+    const std::vector<double> gt = grunwald_weights(s->alpha_t, p->nt - 1);
+    s->ct.assign(p->nt, 0.0);
+    for (int k = 0; k < p->nt; ++k) s->ct[k] = s->frac_t ? gt[k] / hta : (k == 0 ? 1.0 : (k == 1 ? -1.0 : 0.0)) / s->ht;
+  }
+  std::vector<double> tn(p->nt, 0.0);
+  s->tchan_t = tchan_eigs(s->ct, tn);  // T. Chan column c_i = (n - i) t_i / n
   s->tw_t = twiddles(p->nt);
-  // psi = min{ht, hx^alpha, hy^beta} (Sec. 5 with time order 1)
-  s->psi = p->psi_scaling ? std::fmin(s->ht, std::fmin(std::pow(hx, p->alpha), std::pow(hy, p->beta))) : 1.0;
+  if (s->frac_t) {
+    // 2nt circulant embedding of C_t: first column (c_0 .. c_{nt-1}, 0 .. 0)
+    const int L = 2 * p->nt;
+    std::vector<cd> col(L, cd(0, 0));
+    for (int k = 0; k < p->nt; ++k) col[k] = s->ct[k];
+    const std::vector<cd> lam = dft(col);
+    s->lam_t.resize(L);
+    s->lam_tT.resize(L);
+    for (int k = 0; k < L; ++k) {
+      s->lam_t[k] = lam[k] / (double)L;
+      s->lam_tT[k] = std::conj(lam[k]) / (double)L;  // C_t^T embeds as the reversed column
+    }
+    s->tw_t_emb = twiddles(L);
+  }
+  // psi = min{ht^alpha_t, hx^alpha, hy^beta} (Sec. 5)
+  s->psi = p->psi_scaling ? std::fmin(hta, std::fmin(std::pow(hx, p->alpha), std::pow(hy, p->beta))) : 1.0;
   s->e_y = 1.0;
   s->e_u = (p->psi_scaling == 1) ? s->psi : 1.0;
   s->k_u = s->psi * p->ctrl_sign;

@@ -33,7 +33,11 @@ struct Setup {
   int obj_weights = 0;                 // 0: J1 = I, 1: trapezoidal in time
   double dbar_plus = 1, dbar_minus = 1;
   AxisTables x, y;
+  double alpha_t = 1;                  // time order; 1 = implicit Euler
+  bool frac_t = false;                 // alpha_t < 1: the time term is its own line pass
+  std::vector<double> ct;              // first column of the time matrix (length nt)
   std::vector<cd> tchan_t, tw_t;       // time T. Chan eigenvalues, twiddles (length nt)
+  std::vector<cd> lam_t, lam_tT, tw_t_emb;  // 2nt embedding eigenvalues of C_t, C_t^T (with 1/(2nt)), twiddles
   std::vector<double> wts, My, Mu, Mp, invMp;  // per time slice
   std::vector<double> dplus, dminus;   // (ny*nx) copies when var
 };

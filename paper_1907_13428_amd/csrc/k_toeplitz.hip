@@ -283,8 +283,8 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   __syncthreads();
 
   // epilogue: all global operands of a thread are loaded before the first store
-  const double osc = a.oscale ? a.oscale[slice] : 1.0;
-  const double esc = a.extra ? a.escale[slice] : 0.0;
+  const double osc = (a.oscale && !a.row_scale) ? a.oscale[slice] : 1.0;
+  const double esc = (a.extra && !a.row_scale) ? a.escale[slice] : 0.0;
   double dot = 0.0;
   {
     const double2 z2{0.0, 0.0};
@@ -319,8 +319,14 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
       if (ok[k]) {
-        const double2 val{(a.s_sp * sp[k].x + ac[k].x) * osc + esc * ex[k].x,
-                          (a.s_sp * sp[k].y + ac[k].y) * osc + esc * ex[k].y};
+        double o = osc, e = esc;
+        if (a.row_scale) {
+          const int row = (tid + k * NT) / P;
+          o = a.oscale ? a.oscale[row] : 1.0;
+          e = a.extra ? a.escale[row] : 0.0;
+        }
+        const double2 val{(a.s_sp * sp[k].x + ac[k].x) * o + e * ex[k].x,
+                          (a.s_sp * sp[k].y + ac[k].y) * o + e * ex[k].y};
         st2(a.out + sbase + ge[k], val);
         dot += dv[k].x * val.x + dv[k].y * val.y;
       }

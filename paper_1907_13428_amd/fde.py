@@ -41,14 +41,14 @@ class Problem(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("dplus", ctypes.POINTER(ctypes.c_double)), ("dminus", ctypes.POINTER(ctypes.c_double)),
                 ("ctrl_sign", ctypes.c_double), ("psi_scaling", ctypes.c_int32), ("obj_weights", ctypes.c_int32),
-                ("precond_fp32", ctypes.c_int32)]
+                ("precond_fp32", ctypes.c_int32), ("alpha_t", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("delta", ctypes.c_double), ("rho", ctypes.c_double),
                 ("ya", ctypes.c_double), ("yb", ctypes.c_double), ("ua", ctypes.c_double), ("ub", ctypes.c_double),
                 ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
-                ("admm_tol", ctypes.c_double), ("admm_maxit", ctypes.c_int32)]
+                ("admm_tol", ctypes.c_double), ("admm_maxit", ctypes.c_int32), ("pcg_cold_start", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -108,12 +108,13 @@ def _check(status, allow_notconv=True):
 
 
 def make_problem(nx, ny, nt, alpha, beta, *, T=1.0, dplus=None, dminus=None, ctrl_sign=1.0, psi_scaling=1,
-                 obj_weights=0, precond_fp32=0):
+                 obj_weights=0, precond_fp32=0, alpha_t=1.0):
     """Build the C problem struct; the coefficient arrays are kept alive on it."""
     import numpy as np
 
     p = Problem(nx=nx, ny=ny, nt=nt, T=T, alpha=alpha, beta=beta, ctrl_sign=ctrl_sign,
-                psi_scaling=int(psi_scaling), obj_weights=int(obj_weights), precond_fp32=int(precond_fp32))
+                psi_scaling=int(psi_scaling), obj_weights=int(obj_weights), precond_fp32=int(precond_fp32),
+                alpha_t=alpha_t)
     keep = []
     for name, arr in (("dplus", dplus), ("dminus", dminus)):
         if arr is not None:
@@ -127,18 +128,21 @@ def make_problem(nx, ny, nt, alpha, beta, *, T=1.0, dplus=None, dminus=None, ctr
 
 
 def make_params(gamma, *, delta=1.0, rho=1.0, ya=-math.inf, yb=math.inf, ua=-math.inf, ub=math.inf,
-                krylov_tol=1e-10, krylov_maxit=1000, tol_mode=0, admm_tol=1e-6, admm_maxit=100000):
+                krylov_tol=1e-10, krylov_maxit=1000, tol_mode=0, admm_tol=1e-6, admm_maxit=100000,
+                pcg_cold_start=0):
     return Params(gamma=gamma, delta=delta, rho=rho, ya=ya, yb=yb, ua=ua, ub=ub, krylov_tol=krylov_tol,
-                  krylov_maxit=krylov_maxit, tol_mode=tol_mode, admm_tol=admm_tol, admm_maxit=admm_maxit)
+                  krylov_maxit=krylov_maxit, tol_mode=tol_mode, admm_tol=admm_tol, admm_maxit=admm_maxit,
+                  pcg_cold_start=pcg_cold_start)
 
 
 def from_workload(w, precond_fp32=0, **overrides):
     """(Problem, Params) from any object with the workload attributes."""
     prob = make_problem(w.nx, w.ny, w.nt, w.alpha, w.beta, T=w.T, dplus=w.dplus, dminus=w.dminus,
                         ctrl_sign=w.ctrl_sign, psi_scaling=w.psi_scaling, obj_weights=w.obj_weights,
-                        precond_fp32=precond_fp32)
+                        precond_fp32=precond_fp32, alpha_t=getattr(w, "alpha_t", 1.0))
     kw = dict(delta=w.delta, rho=w.rho, ya=w.ya, yb=w.yb, ua=w.ua, ub=w.ub, krylov_tol=w.krylov_tol,
-              krylov_maxit=w.krylov_maxit, admm_tol=w.admm_tol, admm_maxit=w.admm_maxit)
+              krylov_maxit=w.krylov_maxit, admm_tol=w.admm_tol, admm_maxit=w.admm_maxit,
+              tol_mode=getattr(w, "tol_mode", 0), pcg_cold_start=getattr(w, "pcg_cold_start", 0))
     kw.update(overrides)
     return prob, make_params(w.gamma, **kw)
 

@@ -83,12 +83,16 @@ def test_supported_sizes():
             fde.validate(prob, prm)
 
 
-@pytest.mark.parametrize("wl", ["small", "headline_small", "trap"])
+@pytest.mark.parametrize("wl", ["small", "headline_small", "trap", "caputo", "paper_16"])
 def test_host_tables_match_oracle(wl):
     if wl == "small":
         w = W.small()
     elif wl == "headline_small":
         w = W.headline(nx=24, ny=16, nt=8)
+    elif wl == "caputo":
+        w = W.small_mixed(nx=12, ny=8, nt=6, alpha_t=0.4, T=0.7)
+    elif wl == "paper_16":
+        w = W.paper_test(16)
     else:
         w = W.small_mixed(nx=12, ny=8, nt=6, obj_weights=1, rho=1.618, delta=0.4)
     prob, prm = fde.from_workload(w)
@@ -104,6 +108,22 @@ def test_host_tables_match_oracle(wl):
         assert np.max(np.abs(t[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), k
     np.testing.assert_allclose(t["gx"], grunwald.weights(w.alpha, w.nx), rtol=1e-15, atol=1e-300)
     np.testing.assert_allclose(t["gy"], grunwald.weights(w.beta, w.ny), rtol=1e-15, atol=1e-300)
+
+
+@pytest.mark.parametrize("bad", [-0.5, 1.5, float("nan")])
+def test_time_order_validation(bad):
+    prob, prm = fde.from_workload(W.small().replace(alpha_t=bad))
+    with pytest.raises(fde.FdeError) as e:
+        fde.validate(prob, prm)
+    assert e.value.status == fde.FDE_EINVAL and "alpha_t" in str(e.value)
+
+
+def test_time_order_zero_reads_as_implicit_euler():
+    w = W.small()
+    p0, prm = fde.from_workload(w.replace(alpha_t=0.0))
+    p1, _ = fde.from_workload(w)
+    t0, t1 = fde.host_tables(p0, prm), fde.host_tables(p1, prm)
+    assert t0["psi"] == t1["psi"] and np.array_equal(t0["lam_t"], t1["lam_t"])
 
 
 def test_product_path_has_no_cpu_fallback():
