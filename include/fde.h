@@ -141,7 +141,10 @@ fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, 
  * iteration is replayed from a HIP graph captured on a private stream
  * (environment FDE_NO_GRAPH=1 at create time: plain kernel launches).  The
  * column tiles start at the widest variant (FDE_TILES=a,b,c at create time
- * fixes the three variants; see fde_autotune). */
+ * fixes the three variants; see fde_autotune).  Coefficient fields that vary
+ * along x only make every y-line constant-coefficient: the y-passes then use
+ * per-column multipliers, two transforms per column pair instead of three
+ * (FDE_YCOL=0 at create time keeps the general variable-coefficient y-pass). */
 fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream,
                       fde_ctx** out);
 fde_status fde_destroy(fde_ctx* ctx);

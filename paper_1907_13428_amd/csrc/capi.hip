@@ -78,6 +78,7 @@ struct fde_ctx {
   double2 *tcx = nullptr, *tcy = nullptr, *tct = nullptr;
   double2 *ltA = nullptr, *ltTA = nullptr, *twt_emb = nullptr;  // fractional time: 2nt embedding
   bool frac_t = false;
+  bool ycol = false;  // coefficient fields constant along y: per-column y-pass multipliers
   double *dplus = nullptr, *dminus = nullptr;
   double *invMp = nullptr, *My = nullptr, *Mu = nullptr, *Mp = nullptr, *wts = nullptr, *ones = nullptr;
   double2 *dxA = nullptr, *dxB = nullptr, *dyA = nullptr, *dyB = nullptr;  // dL/dalpha, dL/dbeta
@@ -206,6 +207,7 @@ hipError_t ypass(fde_ctx* c, const double* in, const double* acc, double* out, b
   a.lamB = tr ? c->lyTB : c->lyB;
   a.s_sp = s_sp;
   a.tile = c->tile_line_y;
+  a.col_coef = c->ycol ? 1 : 0;
   a.acc = acc;
   a.oscale = osc;
   a.extra = extra;
@@ -883,6 +885,20 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   chk(upload_c(c, &c->tcy, s.y.tchan));
   chk(upload_c(c, &c->tct, s.tchan_t));
   c->frac_t = s.frac_t;
+  // coefficient fields that vary along x only make every y-line constant-coefficient
+  // (FDE_YCOL=0 keeps the general variable-coefficient y-pass)
+  if (c->var) {
+    bool col = true;
+    for (const std::vector<double>* f : {&s.dplus, &s.dminus})
+      for (int j = 1; j < c->ny && col; ++j)
+        for (int i = 0; i < c->nx; ++i)
+          if ((*f)[(size_t)j * c->nx + i] != (*f)[i]) {
+            col = false;
+            break;
+          }
+    const char* ev = std::getenv("FDE_YCOL");
+    c->ycol = col && !(ev && ev[0] == '0');
+  }
   if (s.frac_t) {
     chk(upload_c(c, &c->ltA, s.lam_t));
     chk(upload_c(c, &c->ltTA, s.lam_tT));

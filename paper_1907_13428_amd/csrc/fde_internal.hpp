@@ -64,6 +64,8 @@ struct LinePassArgs {
   int tile;              // y-pass tile variant (autotuned): 0 widest, 1 half, 2 quarter
   int row_scale;         // y-pass kernel run along t (rows = time levels): oscale and
                          // escale are indexed by the row, not the slice
+  int col_coef;          // y-pass: coefficients constant along every y-line; column x
+                         // takes d+[x], d-[x] (row 0 of the planes) inside the multiplier
 };
 
 // launchers (return hipError_t of the launch)

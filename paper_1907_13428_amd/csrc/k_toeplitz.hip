@@ -172,8 +172,15 @@ template <int L, int S = 0> struct YCfg {
   static_assert(Pmax >= 1, "tile");
 };
 
-template <int L, bool VAR, bool TRANS, int S>
+// COL: coefficients constant along each y-line (d+(x), d-(x)).  Column c then
+// applies the single Toeplitz matrix M_c = d+_c G + d-_c G^T (transpose:
+// d+_c G^T + d-_c G), whose embedding multiplier is l_c = d+_c lamA + d-_c lamB.
+// The two real columns packed in Z = F(u0 + i u1) get M_0 u0 + i M_1 u1 from one
+// inverse transform of ((l_0 + l_1)/2) Z[k] + ((l_0 - l_1)/2) conj Z[L-k]
+// (Hermitian separation), so a pair costs two transforms instead of three.
+template <int L, bool VAR, bool TRANS, int S, bool COL = false>
 __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
+  static_assert(!(VAR && COL), "per-column coefficients use the constant-coefficient tile path");
   using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   constexpr int n = L / 2;
@@ -256,17 +263,42 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 
   line_fft<L, E, -1>(v, buf, t, a.tw);
   if constexpr (VAR && TRANS) line_fft<L, E, -1>(w, buf, t, a.tw);
+  if constexpr (COL) {
+    // partner Z[(L - i) mod L] through the pair's LDS stripe
+    constexpr bool WAVE = T <= 64;
+    line_sync<WAVE>();
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int i = t + T * e;
-    const double2 la = a.lamA[i];
-    if constexpr (VAR && TRANS) {
-      v[e] = cadd(cmul(v[e], la), cmul(w[e], a.lamB[i]));
-    } else if constexpr (VAR) {
-      w[e] = cmul(v[e], a.lamB[i]);
-      v[e] = cmul(v[e], la);
-    } else {
-      v[e] = cmul(v[e], la);
+    for (int e = 0; e < E; ++e) buf[t + T * e] = v[e];
+    line_sync<WAVE>();
+#pragma unroll
+    for (int e = 0; e < E; ++e) w[e] = buf[(L - (t + T * e)) % L];
+    line_sync<WAVE>();
+    const int c0 = x0 + 2 * g;
+    const bool h0 = active && c0 < nx, h1 = active && c0 + 1 < nx;
+    const double p0 = h0 ? a.dplus[c0] : 0.0, p1 = h1 ? a.dplus[c0 + 1] : 0.0;
+    const double m0 = h0 ? a.dminus[c0] : 0.0, m1 = h1 ? a.dminus[c0 + 1] : 0.0;
+    const double pb = 0.5 * (p0 + p1), mb = 0.5 * (m0 + m1), pd = 0.5 * (p0 - p1), md = 0.5 * (m0 - m1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t + T * e;
+      const double2 la = a.lamA[i], lb = a.lamB[i];
+      const double2 A{pb * la.x + mb * lb.x, pb * la.y + mb * lb.y};
+      const double2 B{pd * la.x + md * lb.x, pd * la.y + md * lb.y};
+      v[e] = cadd(cmul(A, v[e]), cmul(B, double2{w[e].x, -w[e].y}));
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t + T * e;
+      const double2 la = a.lamA[i];
+      if constexpr (VAR && TRANS) {
+        v[e] = cadd(cmul(v[e], la), cmul(w[e], a.lamB[i]));
+      } else if constexpr (VAR) {
+        w[e] = cmul(v[e], a.lamB[i]);
+        v[e] = cmul(v[e], la);
+      } else {
+        v[e] = cmul(v[e], la);
+      }
     }
   }
   line_fft<L, E, +1>(v, buf, t, a.tw);
@@ -382,7 +414,10 @@ static hipError_t ypass_LS(const LinePassArgs& a, bool tr, bool var, hipStream_t
   const int tiles = (a.nx + 2 * C::P - 1) / (2 * C::P);
   const int blocks = tiles * a.nt;
   if (nb) *nb = blocks;
-  if (var) {
+  if (a.col_coef) {
+    if (tr) k_ypass<L, false, true, S, true><<<blocks, C::NT, 0, s>>>(a);
+    else k_ypass<L, false, false, S, true><<<blocks, C::NT, 0, s>>>(a);
+  } else if (var) {
     if (tr) k_ypass<L, true, true, S><<<blocks, C::NT, 0, s>>>(a);
     else k_ypass<L, true, false, S><<<blocks, C::NT, 0, s>>>(a);
   } else {

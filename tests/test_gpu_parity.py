@@ -303,6 +303,31 @@ def test_admm_paper_control_sign_exact_zero_optimum():
     assert np.abs(y).max() <= 1e-5 and np.abs(u).max() <= 1e-5, (np.abs(y).max(), np.abs(u).max())
 
 
+@pytest.mark.parametrize("ycol", ["1", "0"])
+def test_x_only_coefficients_both_y_pass_paths(monkeypatch, ycol):
+    """Coefficient fields varying along x only (d+ and d- both): the
+    per-column y-pass (two transforms per column pair, Hermitian separation)
+    and the general variable-coefficient y-pass (FDE_YCOL=0) both match the
+    oracle; ragged column tiles (nx = 24) and a radix-3 y length."""
+    banner("x-only coefficients, FDE_YCOL", ycol)
+    monkeypatch.setenv("FDE_YCOL", ycol)
+    w = W.small(nx=24, ny=48, nt=6).replace(alpha=1.35, beta=1.65)
+    w.dplus = W.coef_sine_x(24, 48)
+    w.dminus = W.coef_sine_x(24, 48, amp=-0.3)
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    v = W.random_field(w.shape, 51)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        y = zeros(w.shape)
+        for tr, ref in ((False, op.apply_D(d, v)), (True, op.apply_DT(d, v))):
+            ctx.apply_A(dev(v), y, tr)
+            assert rel(host(y), ref) <= 1e-11, (tr, rel(host(y), ref))
+        ctx.apply_S(dev(v), y)
+        assert rel(host(y), admm.apply_S(d, sc, v)) <= 1e-11
+    _admm_fixed(w.replace(ua=-5.0, ub=5.0), 40)
+
+
 def test_admm_headline_shape_small():
     banner("admm headline 12x12x6")
     w = W.headline(nx=12, ny=12, nt=6)
