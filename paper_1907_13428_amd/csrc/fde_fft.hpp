@@ -174,7 +174,7 @@ constexpr int pick_radix(int rem, int E) {
 constexpr int default_E(int L) {
   return (L % 3 == 0) ? (L >= 24 ? 24 : L)
          : (L <= 16)  ? L
-         : (L == 128 || L == 256) ? 16
+         : (L == 128) ? 16
                                   : 8;
 }
 
