@@ -100,16 +100,21 @@ def copy_calibration(torch, reps=5):
     return {"bytes_per_copy": 2 * COPY_BYTES, "us": round(us, 2), "GB/s": round(2 * COPY_BYTES / us / 1e3, 1)}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ypass_BT_headline_256x256x64.json")
-KERNEL_SOURCES = ["paper_1907_13428_amd/csrc/k_toeplitz.hip", "paper_1907_13428_amd/csrc/fde_fft.hpp",
-                  "paper_1907_13428_amd/csrc/fde_internal.hpp", "paper_1907_13428_amd/csrc/fde_reduce.hpp"]
+COMMON_SOURCES = ["paper_1907_13428_amd/csrc/fde_fft.hpp", "paper_1907_13428_amd/csrc/fde_internal.hpp",
+                  "paper_1907_13428_amd/csrc/fde_reduce.hpp"]
 
 
-def kernel_source_hash():
+def kernel_sources(pass_name):
+    """The source files that define the kernel of a PCG pass."""
+    own = "k_toeplitz.hip" if pass_name.split("_")[0] in ("xpass", "ypass") else "k_precond.hip"
+    return ["paper_1907_13428_amd/csrc/" + own] + COMMON_SOURCES
+
+
+def kernel_source_hash(pass_name):
     import hashlib
 
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in kernel_sources(pass_name):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -117,16 +122,19 @@ def kernel_source_hash():
 
 def measured_traffic(pass_name, tile_width):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE passes scaled by the copy kernel), or
-    None when there is none for this pass and tile or the kernel sources have
-    changed since the counters were taken."""
+    summary profiles/traffic_<pass>_headline_256x256x64.json (FETCH_SIZE and
+    WRITE_SIZE passes scaled by the copy kernel), or None when there is none
+    for this pass (and y-pass tile width) or the kernel sources have changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{pass_name}_headline_256x256x64.json")
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if (rec.get("pass") != pass_name or rec.get("tile_width") != tile_width
-            or rec.get("source_sha256") != kernel_source_hash()):
+    if rec.get("pass") != pass_name or rec.get("source_sha256") != kernel_source_hash(pass_name):
+        return None
+    if pass_name.startswith("ypass") and rec.get("tile_width") != tile_width:
         return None
     return rec.get("traffic_bytes")
 
