@@ -15,6 +15,15 @@ e_u = psi; e_y = 1), one iteration j is:
   5. w_y += (rho/delta) e_y (y - z_y),  w_u += (rho/delta) e_u (u - z_u)
   6. stop when max(|B y + k_u u - h|_inf, |y - z_y|_inf, |u - z_u|_inf) <= tol
 
+Algorithm 2 (generalized ADMM, Sec. 3.3.2) adds the proximal term
+1/2 (y - y^j)^T R_y (y - y^j) + 1/2 (u - u^j)^T R_u (u - u^j) to the x-step,
+with R_y = c_y I - J1 and R_u = c_u I - J2.  It enters beside J1 and J2 under
+the same factor rho, so the (1,1) and (2,2) blocks become the scaled
+identities rho (c_y + e_y^2/delta) I and rho (c_u + e_u^2/delta) I (the
+printed coefficient matrix of the generalized x-step), and step 1 gains
+rho R_y y^j in R_y and rho R_u u^j in R_u.  The printed algorithm omits the
+1/2 on the u term; the printed coefficient matrix fixes it.
+
 Steps 1-3 are the elimination of u and p from the merged system (3.8); the
 sign of the M_u^{-1} term in r is "+" (eliminating u from the third block row
 gives + k_u M_u^{-1} R_u; the printed "-" does not reproduce the block solve,
@@ -45,6 +54,8 @@ class Scalars:
     My: np.ndarray  # (nt,)
     Mu: np.ndarray  # (nt,)
     Mp: np.ndarray  # (nt,)
+    cy: float = 0.0  # Algorithm 2 constants (0 under Algorithm 1)
+    cu: float = 0.0
 
 
 def objective_weights(w) -> np.ndarray:
@@ -56,16 +67,32 @@ def objective_weights(w) -> np.ndarray:
     return wts
 
 
+def prox_constants(w, wts):
+    """c_y, c_u of Algorithm 2 (Sec. 3.3.2).  The algorithm asks for R_y, R_u
+    positive definite; c = max diag J (R semi-definite, zero where J is at its
+    maximum) is accepted too and is what 0 selects."""
+    cy = w.prox_cy if w.prox_cy > 0 else float(np.max(wts))
+    cu = w.prox_cu if w.prox_cu > 0 else w.gamma * float(np.max(wts))
+    return cy, cu
+
+
 def scalars(w, d: op.Disc) -> Scalars:
     psi = op.psi_scale(d) if w.psi_scaling else 1.0
     e_y = 1.0
     e_u = psi if w.psi_scaling == 1 else 1.0
     k_u = psi * w.ctrl_sign
     wts = objective_weights(w)
-    My = w.rho * (wts + e_y ** 2 / w.delta)
-    Mu = w.rho * (w.gamma * wts + e_u ** 2 / w.delta)
+    cy = cu = 0.0
+    if getattr(w, "prox", 0):
+        # Algorithm 2: J1 + R_y = c_y I, J2 + R_u = c_u I
+        cy, cu = prox_constants(w, wts)
+        My = w.rho * (cy + e_y ** 2 / w.delta) * np.ones(w.nt)
+        Mu = w.rho * (cu + e_u ** 2 / w.delta) * np.ones(w.nt)
+    else:
+        My = w.rho * (wts + e_y ** 2 / w.delta)
+        Mu = w.rho * (w.gamma * wts + e_u ** 2 / w.delta)
     Mp = k_u ** 2 / Mu + w.delta / w.rho
-    return Scalars(psi, e_y, e_u, k_u, wts, My, Mu, Mp)
+    return Scalars(psi, e_y, e_u, k_u, wts, My, Mu, Mp, cy, cu)
 
 
 def tcol(a):
@@ -159,6 +186,9 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
     J1 = tcol(sc.wts)
     My, Mu, Mp = tcol(sc.My), tcol(sc.Mu), tcol(sc.Mp)
     rho, delta = w.rho, w.delta
+    prox = bool(getattr(w, "prox", 0))
+    if prox:
+        Rdy, Rdu = sc.cy - J1, sc.cu - w.gamma * J1  # diagonals of R_y, R_u
 
     Schol = None
     if solver == "direct":
@@ -176,8 +206,15 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
     j = 0
     for j in range(1, maxit + 1):
         # 1. right-hand sides of the merged system (3.8)
-        Ry = rho * (J1 * yhat - sc.e_y * wy + sc.e_y ** 2 * zy / delta) + (1 - rho) * apply_BT(d, sc, p)
-        Ru = rho * (-sc.e_u * wu + sc.e_u ** 2 * zu / delta) + (1 - rho) * sc.k_u * p
+        if prox:
+            # Algorithm 2: the proximal terms' share of the right-hand side, at
+            # the previous iterate (y, u)
+            Ry = (rho * (J1 * yhat - sc.e_y * wy + sc.e_y ** 2 * zy / delta + Rdy * y)
+                  + (1 - rho) * apply_BT(d, sc, p))
+            Ru = rho * (-sc.e_u * wu + sc.e_u ** 2 * zu / delta + Rdu * u) + (1 - rho) * sc.k_u * p
+        else:
+            Ry = rho * (J1 * yhat - sc.e_y * wy + sc.e_y ** 2 * zy / delta) + (1 - rho) * apply_BT(d, sc, p)
+            Ru = rho * (-sc.e_u * wu + sc.e_u ** 2 * zu / delta) + (1 - rho) * sc.k_u * p
         r = sc.k_u * Ru / Mu - h + (delta / rho) * p
         b = Ry - apply_BT(d, sc, r / Mp)
         # 2. normal equations (3.9)
@@ -215,9 +252,11 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
                       r_p=r_p, r_y=r_y, r_u=r_u, converged=converged, psi=sc.psi, e_u=sc.e_u)
 
 
-def xstep_block_solve(w, yhat, zy, zu, p, wy, wu, g=None):
+def xstep_block_solve(w, yhat, zy, zu, p, wy, wu, g=None, y_prev=None, u_prev=None):
     """Reference for steps 1-3: solve the merged 3x3 block system (3.8) densely
-    for (y, u, p+) in the scaled variables (tiny grids only)."""
+    for (y, u, p+) in the scaled variables (tiny grids only).  With w.prox the
+    system is the generalized x-step of Sec. 3.3.2: scaled-identity (1,1) and
+    (2,2) blocks and the proximal terms at (y_prev, u_prev) on the right."""
     d = op.disc_from(w)
     sc = scalars(w, d)
     N = w.N
@@ -227,15 +266,24 @@ def xstep_block_solve(w, yhat, zy, zu, p, wy, wu, g=None):
     rho, delta = w.rho, w.delta
     I = np.eye(N)
     g = np.zeros(N) if g is None else g.ravel()
+    if getattr(w, "prox", 0):
+        A11 = rho * (sc.cy + sc.e_y ** 2 / delta) * I
+        A22 = rho * (sc.cu + sc.e_u ** 2 / delta) * I
+        ex_y = rho * (sc.cy - J1) * y_prev.ravel()
+        ex_u = rho * (sc.cu - J2) * u_prev.ravel()
+    else:
+        A11 = np.diag(rho * (J1 + sc.e_y ** 2 / delta))
+        A22 = np.diag(rho * (J2 + sc.e_u ** 2 / delta))
+        ex_y = ex_u = 0.0
     K = np.block([
-        [np.diag(rho * (J1 + sc.e_y ** 2 / delta)), np.zeros((N, N)), Bm.T],
-        [np.zeros((N, N)), np.diag(rho * (J2 + sc.e_u ** 2 / delta)), sc.k_u * I],
+        [A11, np.zeros((N, N)), Bm.T],
+        [np.zeros((N, N)), A22, sc.k_u * I],
         [Bm, sc.k_u * I, -(delta / rho) * I],
     ])
     rhs = np.concatenate([
         rho * (J1 * yhat.ravel() - sc.e_y * wy.ravel() + sc.e_y ** 2 * zy.ravel() / delta)
-        + (1 - rho) * Bm.T @ p.ravel(),
-        rho * (-sc.e_u * wu.ravel() + sc.e_u ** 2 * zu.ravel() / delta) + (1 - rho) * sc.k_u * p.ravel(),
+        + ex_y + (1 - rho) * Bm.T @ p.ravel(),
+        rho * (-sc.e_u * wu.ravel() + sc.e_u ** 2 * zu.ravel() / delta) + ex_u + (1 - rho) * sc.k_u * p.ravel(),
         sc.psi * g - (delta / rho) * p.ravel(),
     ])
     sol = np.linalg.solve(K, rhs)

@@ -78,8 +78,13 @@ def precond_tables(w, d: Disc):
     e_u = psi if w.psi_scaling == 1 else 1.0
     k_u = psi * w.ctrl_sign
     jbar = 1.0
-    a = w.rho * (jbar + e_y ** 2 / w.delta)
-    mbar_p = k_u ** 2 / (w.rho * (w.gamma * jbar + e_u ** 2 / w.delta)) + w.delta / w.rho
+    cy, cu = jbar, w.gamma * jbar
+    if getattr(w, "prox", 0):
+        # Algorithm 2: the (1,1), (2,2) blocks are c_y I and c_u I exactly
+        cy = w.prox_cy if w.prox_cy > 0 else jbar
+        cu = w.prox_cu if w.prox_cu > 0 else w.gamma * jbar
+    a = w.rho * (cy + e_y ** 2 / w.delta)
+    mbar_p = k_u ** 2 / (w.rho * (cu + e_u ** 2 / w.delta)) + w.delta / w.rho
     return dict(lam_x=lam_x, lam_y=lam_y, lam_t=lam_t, col_x=col_x, col_y=col_y, col_t=col_t,
                 psi=psi, a=a, mbar_p=mbar_p)
 

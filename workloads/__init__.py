@@ -55,6 +55,9 @@ class Workload:
     alpha_t: float = 1.0  # order of the time derivative in (0, 1]; 1 = implicit Euler
     tol_mode: int = 0  # 0: fixed Krylov tolerance; 1: the dynamic rule of Sec. 6.1
     pcg_cold_start: int = 0  # 0: PCG starts from the previous y; 1: from zero
+    prox: int = 0  # 0: Algorithm 1; 1: generalized ADMM (Algorithm 2), R_y = c_y I - J1, R_u = c_u I - J2
+    prox_cy: float = 0.0  # c_y (0: the smallest admissible, max diag J1)
+    prox_cu: float = 0.0  # c_u (0: the smallest admissible, max diag J2)
     yhat: Optional[np.ndarray] = None  # (nt, ny, nx)
     dplus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
     dminus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
