@@ -98,6 +98,17 @@ typedef struct {
   int32_t admm_maxit;     /* > 0                                                */
   int32_t pcg_cold_start; /* 0: each x-step's PCG starts from the previous y;
                              1: from zero (MATLAB pcg's default, Sec. 6.1)     */
+  int32_t prox;           /* 0: Algorithm 1.  1: the generalized ADMM of
+                             Sec. 3.3.2 (Algorithm 2): the x-step adds
+                             1/2|y - y^j|^2_{R_y} + 1/2|u - u^j|^2_{R_u} with
+                             R_y = c_y I - J1, R_u = c_u I - J2, so its (1,1)
+                             and (2,2) blocks are the scaled identities
+                             rho (c_y + e_y^2/delta) I, rho (c_u + e_u^2/delta) I
+                             and the preconditioner's scalars are exact.
+                             Needs rho in (0, 1].                            */
+  double prox_cy;         /* c_y: 0 selects max diag J1 = 1 (R_y semi-definite,
+                             zero off the last time block); else >= 1        */
+  double prox_cu;         /* c_u: 0 selects gamma; else >= gamma              */
 } fde_admm_params;
 
 typedef struct {

@@ -546,6 +546,10 @@ fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* 
   k.yb = q.yb;
   k.ua = q.ua;
   k.ub = q.ub;
+  k.prox = q.prox;
+  k.cy = s.cy;
+  k.cu = s.cu;
+  k.gamma = q.gamma;
   k.wts = c->wts;
   k.Mu = c->Mu;
   k.Mp = c->Mp;

@@ -168,6 +168,8 @@ struct AdmmConsts {
   int plane;  // nx * ny
   int nt;
   double rho, delta, e_y, e_u, k_u, ya, yb, ua, ub;
+  int prox;              // Algorithm 2: proximal terms rho R (y^j, u^j) in the right-hand side
+  double cy, cu, gamma;  // R_y = cy - wts[t], R_u = cu - gamma wts[t]
   const double* wts;  // per time slice J1 diagonal
   const double* Mu;   // per time slice
   const double* Mp;

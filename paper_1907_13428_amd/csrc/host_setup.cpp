@@ -47,6 +47,19 @@ int validate_params(const fde_admm_params* q, std::string* msg) {
   if (q->krylov_maxit <= 0) { *msg = "krylov_maxit must be > 0"; return FDE_EINVAL; }
   if (q->pcg_cold_start != 0 && q->pcg_cold_start != 1) { *msg = "pcg_cold_start must be 0 or 1"; return FDE_EINVAL; }
   if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
+  if (q->prox != 0 && q->prox != 1) { *msg = "prox must be 0 or 1"; return FDE_EINVAL; }
+  if (q->prox) {
+    // Algorithm 2 takes its step in (0, 1]; R_y, R_u must not be indefinite
+    if (!(q->rho <= 1.0)) { *msg = "prox = 1 (Algorithm 2) needs rho in (0, 1]"; return FDE_EINVAL; }
+    if (!finite(q->prox_cy) || !(q->prox_cy == 0.0 || q->prox_cy >= 1.0)) {
+      *msg = "prox_cy must be 0 or >= max diag J1 = 1";
+      return FDE_EINVAL;
+    }
+    if (!finite(q->prox_cu) || !(q->prox_cu == 0.0 || q->prox_cu >= q->gamma)) {
+      *msg = "prox_cu must be 0 or >= gamma";
+      return FDE_EINVAL;
+    }
+  }
   if (!(q->admm_tol >= 0) || !finite(q->admm_tol)) { *msg = "admm_tol must be >= 0"; return FDE_EINVAL; }
   if (q->admm_maxit <= 0) { *msg = "admm_maxit must be > 0"; return FDE_EINVAL; }
   return FDE_OK;
@@ -229,16 +242,27 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
   s->Mu.resize(nt);
   s->Mp.resize(nt);
   s->invMp.resize(nt);
+  // Algorithm 2 (Sec. 3.3.2): J1 + R_y = cy I and J2 + R_u = cu I replace J1, J2
+  // in the x-step's diagonal blocks; max diag J1 = 1 for both weightings
+  s->cy = s->cu = 0.0;
+  if (q->prox) {
+    s->cy = q->prox_cy > 0 ? q->prox_cy : 1.0;
+    s->cu = q->prox_cu > 0 ? q->prox_cu : q->gamma;
+  }
   for (int k = 0; k < nt; ++k) {
-    s->My[k] = q->rho * (s->wts[k] + s->e_y * s->e_y / q->delta);
-    s->Mu[k] = q->rho * (q->gamma * s->wts[k] + s->e_u * s->e_u / q->delta);
+    const double jy = q->prox ? s->cy : s->wts[k];
+    const double ju = q->prox ? s->cu : q->gamma * s->wts[k];
+    s->My[k] = q->rho * (jy + s->e_y * s->e_y / q->delta);
+    s->Mu[k] = q->rho * (ju + s->e_u * s->e_u / q->delta);
     s->Mp[k] = s->k_u * s->k_u / s->Mu[k] + q->delta / q->rho;
     s->invMp[k] = 1.0 / s->Mp[k];
   }
-  // preconditioner: J1 approximated by jbar = 1 (eq. (3.10) with circulant blocks)
+  // preconditioner: J1 approximated by jbar = 1 (eq. (3.10) with circulant
+  // blocks); under Algorithm 2 the blocks cy I, cu I are taken exactly
   const double jbar = 1.0;
-  s->a = q->rho * (jbar + s->e_y * s->e_y / q->delta);
-  const double mbar = s->k_u * s->k_u / (q->rho * (q->gamma * jbar + s->e_u * s->e_u / q->delta)) + q->delta / q->rho;
+  const double ay = q->prox ? s->cy : jbar, au = q->prox ? s->cu : q->gamma * jbar;
+  s->a = q->rho * (ay + s->e_y * s->e_y / q->delta);
+  const double mbar = s->k_u * s->k_u / (q->rho * (au + s->e_u * s->e_u / q->delta)) + q->delta / q->rho;
   s->inv_mbar = 1.0 / mbar;
 }
 

@@ -192,19 +192,28 @@ hipError_t launch_pupdate(int64_t n, const double* z, double* p, double* scal, c
 //   r  = k_u Ru / Mu - psi g + (delta/rho) p
 //   v  = (1-rho) p - r / Mp         (b = B^T v + c)
 //   c  = rho (J1 yhat - e_y wy + e_y^2 zy / delta)
+// and under Algorithm 2 (Sec. 3.3.2) rho R_u u and rho R_y y, at the previous
+// iterate, join Ru and c.
 __global__ __launch_bounds__(kBlock) void k_admm_rhs(AdmmConsts k, AdmmFields f, double psi) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const double rho = k.rho, delta = k.delta;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < k.n; i += stride) {
     const int t = (int)(i / k.plane);
     const double p = f.p[i];
-    const double Ru = rho * (-k.e_u * f.wu[i] + k.e_u * k.e_u * f.zu[i] / delta) + (1.0 - rho) * k.k_u * p;
+    double xu = -k.e_u * f.wu[i] + k.e_u * k.e_u * f.zu[i] / delta;
+    double xy = k.wts[t] * f.yhat[i] - k.e_y * f.wy[i] + k.e_y * k.e_y * f.zy[i] / delta;
+    if (k.prox) {
+      // Algorithm 2: R_u u^j and R_y y^j at the previous iterate
+      xu += (k.cu - k.gamma * k.wts[t]) * f.u[i];
+      xy += (k.cy - k.wts[t]) * f.y[i];
+    }
+    const double Ru = rho * xu + (1.0 - rho) * k.k_u * p;
     const double gv = f.g ? f.g[i] : 0.0;
     const double r = k.k_u * Ru / k.Mu[t] - psi * gv + (delta / rho) * p;
     f.Ru[i] = Ru;
     f.r[i] = r;
     f.v[i] = (1.0 - rho) * p - r / k.Mp[t];
-    f.c[i] = rho * (k.wts[t] * f.yhat[i] - k.e_y * f.wy[i] + k.e_y * k.e_y * f.zy[i] / delta);
+    f.c[i] = rho * xy;
   }
 }
 

@@ -83,7 +83,7 @@ def test_supported_sizes():
             fde.validate(prob, prm)
 
 
-@pytest.mark.parametrize("wl", ["small", "headline_small", "trap", "caputo", "paper_16"])
+@pytest.mark.parametrize("wl", ["small", "headline_small", "trap", "caputo", "paper_16", "prox", "prox_default"])
 def test_host_tables_match_oracle(wl):
     if wl == "small":
         w = W.small()
@@ -93,6 +93,10 @@ def test_host_tables_match_oracle(wl):
         w = W.small_mixed(nx=12, ny=8, nt=6, alpha_t=0.4, T=0.7)
     elif wl == "paper_16":
         w = W.paper_test(16)
+    elif wl == "prox":
+        w = W.small_mixed(nx=12, ny=8, nt=6, obj_weights=1, rho=0.8, delta=0.4, prox=1, prox_cy=1.7, prox_cu=3e-3)
+    elif wl == "prox_default":
+        w = W.small_mixed(nx=12, ny=8, nt=6, obj_weights=1, prox=1)
     else:
         w = W.small_mixed(nx=12, ny=8, nt=6, obj_weights=1, rho=1.618, delta=0.4)
     prob, prm = fde.from_workload(w)
@@ -116,6 +120,26 @@ def test_time_order_validation(bad):
     with pytest.raises(fde.FdeError) as e:
         fde.validate(prob, prm)
     assert e.value.status == fde.FDE_EINVAL and "alpha_t" in str(e.value)
+
+
+@pytest.mark.parametrize("field,value,frag", [("prox", 2, "prox must"), ("rho", 1.2, "rho in (0, 1]"),
+                                              ("prox_cy", 0.5, "prox_cy"), ("prox_cy", -1.0, "prox_cy"),
+                                              ("prox_cy", math.inf, "prox_cy"), ("prox_cu", 0.5e-4, "prox_cu"),
+                                              ("prox_cu", math.nan, "prox_cu")])
+def test_generalized_admm_validation(field, value, frag):
+    """Algorithm 2: step in (0, 1]; R_y = c_y I - J1 and R_u = c_u I - J2 not
+    indefinite (c_y >= 1, c_u >= gamma, or 0 for those values)."""
+    w = W.small(prox=1)  # gamma = 1e-4
+    prob, prm = fde.from_workload(w)
+    fde.validate(prob, prm)
+    setattr(prm, field, value)
+    with pytest.raises(fde.FdeError) as e:
+        fde.validate(prob, prm)
+    assert e.value.status == fde.FDE_EINVAL and frag in str(e.value)
+    # the same values are ignored under Algorithm 1 (rho up to the golden ratio)
+    if field != "prox":
+        prm.prox = 0
+        fde.validate(prob, prm)
 
 
 def test_time_order_zero_reads_as_implicit_euler():
