@@ -10,6 +10,10 @@ scalar jbar = 1 (the paper notes J is nearly a scaled identity, Sec. 4),
     S~ = rho (jbar + e_y^2/delta) I + C_3(B)^* C_3(B) / mbar_p,
     mbar_p = k_u^2 / (rho (gamma jbar + e_u^2/delta)) + delta/rho,
 so S~ has eigenvalues s = a + |Lambda|^2 / mbar_p in the DFT basis.
+Sec. 3.2.2, eq. (3.11): the matching approximation with the same blocks,
+    S^ = D^ M2~^{-1} D^*,  D^ = C_3(B)^* + (M1~ M2~)^{1/2},  M1~ = a, M2~ = mbar_p,
+is a circulant too, with eigenvalues |Lambda + sqrt(a mbar_p)|^2 / mbar_p
+(precond_kind = 1).
 
 DFT convention: lambda_k = sum_m c_m exp(-2 pi i k m / n), computed here by the
 explicit O(n^2) sum; the circulant acts as C x = F^{-1} diag(lambda) F x with
@@ -86,13 +90,17 @@ def precond_tables(w, d: Disc):
     a = w.rho * (cy + e_y ** 2 / w.delta)
     mbar_p = k_u ** 2 / (w.rho * (cu + e_u ** 2 / w.delta)) + w.delta / w.rho
     return dict(lam_x=lam_x, lam_y=lam_y, lam_t=lam_t, col_x=col_x, col_y=col_y, col_t=col_t,
-                psi=psi, a=a, mbar_p=mbar_p)
+                psi=psi, a=a, mbar_p=mbar_p, kind=int(getattr(w, "precond_kind", 0)))
 
 
 def precond_symbol(tab) -> np.ndarray:
-    """s[k, j, i] = a + |psi (lam_t[k] - lam_y[j] - lam_x[i])|^2 / mbar_p."""
+    """s[k, j, i] = a + |Lam|^2 / mbar_p (S~, eq. (3.10)) or
+    |Lam + sqrt(a mbar_p)|^2 / mbar_p (S^, eq. (3.11)), with
+    Lam = psi (lam_t[k] - lam_y[j] - lam_x[i])."""
     lam = tab["psi"] * (tab["lam_t"][:, None, None] - tab["lam_y"][None, :, None]
                         - tab["lam_x"][None, None, :])
+    if tab.get("kind", 0) == 1:
+        return np.abs(lam + np.sqrt(tab["a"] * tab["mbar_p"])) ** 2 / tab["mbar_p"]
     return tab["a"] + np.abs(lam) ** 2 / tab["mbar_p"]
 
 

@@ -96,3 +96,46 @@ def test_precond_matches_dense_schur_approximation(var):
 def test_coefficient_mean_of_sine_field_is_one():
     d = W.coef_sine_x(256, 256)
     assert abs(np.mean(d) - 1.0) < 1e-14
+
+
+def _c3(tab, w):
+    Cx, Cy, Ct = (pc.circulant(tab["col_x"]), pc.circulant(tab["col_y"]), pc.circulant(tab["col_t"]))
+    nx, ny, nt = w.nx, w.ny, w.nt
+    return tab["psi"] * (np.kron(Ct, np.eye(nx * ny)) - np.kron(np.eye(nt), np.kron(Cy, np.eye(nx)))
+                         - np.kron(np.eye(nt * ny), Cx))
+
+
+@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("prox", [0, 1])
+def test_matching_precond_matches_dense_eq_3_11(var, prox):
+    """precond_kind = 1 solves with S^ = D^ M2~^{-1} D^*, D^ = C_3^* + (M1~ M2~)^{1/2},
+    assembled densely from the 1-D T. Chan circulants."""
+    w = _tiny(var).replace(precond_kind=1, prox=prox, rho=0.9 if prox else 1.3)
+    tab = pc.precond_tables(w, op.disc_from(w))
+    assert tab["kind"] == 1
+    C3 = _c3(tab, w)
+    c = np.sqrt(tab["a"] * tab["mbar_p"])
+    Dh = C3.T + c * np.eye(w.N)
+    S_h = Dh @ Dh.T / tab["mbar_p"]
+    r = W.random_field(w.shape, 5)
+    z = pc.apply_precond(tab, r)
+    np.testing.assert_allclose(S_h @ z.ravel(), r.ravel(), rtol=1e-11, atol=1e-11)
+
+
+def test_matching_theorem_interval_for_circulant_constraints():
+    """Thm 3.5 (second part): with scalar (1,1)/(2,2) blocks and a constraint
+    matrix whose symmetric part is positive semi-definite, S^{-1} S has its
+    eigenvalues in [1/2, 1].  Taking the constraint matrix to be C_3 itself,
+    S is exactly S~ = a I + C_3^T C_3 / mbar_p."""
+    w = _tiny(False)
+    tab = pc.precond_tables(w, op.disc_from(w))
+    C3 = _c3(tab, w)
+    assert np.linalg.eigvalsh(C3 + C3.T).min() >= -1e-12  # D + D^* positive semi-definite
+    S = tab["a"] * np.eye(w.N) + C3.T @ C3 / tab["mbar_p"]
+    c = np.sqrt(tab["a"] * tab["mbar_p"])
+    Dh = C3.T + c * np.eye(w.N)
+    S_h = Dh @ Dh.T / tab["mbar_p"]
+    ev = np.linalg.eigvals(np.linalg.solve(S_h, S)).real
+    assert ev.min() >= 0.5 - 1e-12 and ev.max() <= 1.0 + 1e-12
+    # and the interval is not trivially [1, 1]: S^ differs from S~
+    assert ev.min() < 0.99
