@@ -109,6 +109,11 @@ typedef struct {
   double prox_cy;         /* c_y: 0 selects max diag J1 = 1 (R_y semi-definite,
                              zero off the last time block); else >= 1        */
   double prox_cu;         /* c_u: 0 selects gamma; else >= gamma              */
+  int32_t precond_kind;   /* 0: S~ of eq. (3.10), a I + C^* C / mbar_p;
+                             1: the matching approximation S^ of eq. (3.11)
+                             with the same blocks, (C^* + c)(C + c) / mbar_p,
+                             c = (a mbar_p)^{1/2} (C the 3-level T. Chan
+                             circulant of B, eq. (5.2))                       */
 } fde_admm_params;
 
 typedef struct {

@@ -291,6 +291,7 @@ fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
   a.psi = c->su.psi;
   a.a = c->su.a;
   a.inv_mbar = c->su.inv_mbar;
+  a.match2 = c->su.match2;
   a.inv_n = 1.0 / (double)c->N;
   a.scal = c->scal;
   a.tile_y = c->tile_pre_y;

@@ -89,6 +89,7 @@ struct PrecondArgs {
   const double2* lam_y;
   const double2* lam_t;
   double psi, a, inv_mbar, inv_n;  // s = a + |psi (lt - ly - lx)|^2 * inv_mbar; 1/(nx ny nt)
+  double match2;                   // + match2 * Re(psi (lt - ly - lx)): the matching form (0: S~)
   int div_mode;  // 0: divide by s (S~^{-1}); 1: multiply by 1/conj(psi (lt - ly - lx)) (C^{-T})
   int tile_y, tile_t;  // column-tile variants of the y and t passes (autotuned)
   // fused PCG pieces

@@ -48,6 +48,7 @@ int validate_params(const fde_admm_params* q, std::string* msg) {
   if (q->pcg_cold_start != 0 && q->pcg_cold_start != 1) { *msg = "pcg_cold_start must be 0 or 1"; return FDE_EINVAL; }
   if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
   if (q->prox != 0 && q->prox != 1) { *msg = "prox must be 0 or 1"; return FDE_EINVAL; }
+  if (q->precond_kind != 0 && q->precond_kind != 1) { *msg = "precond_kind must be 0 or 1"; return FDE_EINVAL; }
   if (q->prox) {
     // Algorithm 2 takes its step in (0, 1]; R_y, R_u must not be indefinite
     if (!(q->rho <= 1.0)) { *msg = "prox = 1 (Algorithm 2) needs rho in (0, 1]"; return FDE_EINVAL; }
@@ -264,6 +265,8 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
   s->a = q->rho * (ay + s->e_y * s->e_y / q->delta);
   const double mbar = s->k_u * s->k_u / (q->rho * (au + s->e_u * s->e_u / q->delta)) + q->delta / q->rho;
   s->inv_mbar = 1.0 / mbar;
+  // eq. (3.11): |L + (a mbar)^{1/2}|^2 / mbar = a + |L|^2 / mbar + 2 (a / mbar)^{1/2} Re L
+  s->match2 = q->precond_kind == 1 ? 2.0 * std::sqrt(s->a / mbar) : 0.0;
 }
 
 int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::string* msg) {

@@ -30,6 +30,7 @@ struct Setup {
   double T = 1, ht = 0, psi = 1, e_y = 1, e_u = 1, k_u = 1;
   double a = 0, inv_mbar = 0;          // preconditioner scalars
   double cy = 0, cu = 0;               // Algorithm 2: J1 + R_y = cy I, J2 + R_u = cu I (0: Algorithm 1)
+  double match2 = 0;                   // matching approximation: 2 (a / mbar)^{1/2} (0: S~)
   bool var = false;                    // variable coefficient fields present
   int obj_weights = 0;                 // 0: J1 = I, 1: trapezoidal in time
   double dbar_plus = 1, dbar_minus = 1;

@@ -3,6 +3,9 @@
 // is diagonalised by the 3-D DFT, with eigenvalues
 //     s(kx, ky, kt) = a + |psi (lam_t[kt] - lam_y[ky] - lam_x[kx])|^2 / mbar_p
 // computed in registers from the three 1-D tables (no N-sized eigen array).
+// The matching approximation S^ of eq. (3.11) with the same blocks is the
+// circulant (C_3^* + c)(C_3 + c) / mbar_p, c = (a mbar_p)^{1/2}: its eigenvalue
+// adds 2 (a / mbar_p)^{1/2} Re(psi (lam_t - lam_y - lam_x)) to s.
 //
 // Passes (each one HBM sweep of the half spectrum [nt][ny][H], H = nx/2 + 1):
 //   1. x: real -> half spectrum, two real lines packed per complex FFT of
@@ -245,7 +248,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
       const double re = a.psi * (lt.x - ly.x - lx.x);
       const double im = a.psi * (lt.y - ly.y - lx.y);
       if constexpr (MODE == 1) {
-        const double s = a.a + (re * re + im * im) * a.inv_mbar;
+        const double s = a.a + (re * re + im * im) * a.inv_mbar + a.match2 * re;
         const TS f = TS(a.inv_n / s);
         v[e] = V{v[e].x * f, v[e].y * f};
       } else {

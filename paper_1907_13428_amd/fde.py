@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
                 ("ya", ctypes.c_double), ("yb", ctypes.c_double), ("ua", ctypes.c_double), ("ub", ctypes.c_double),
                 ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("admm_tol", ctypes.c_double), ("admm_maxit", ctypes.c_int32), ("pcg_cold_start", ctypes.c_int32),
-                ("prox", ctypes.c_int32), ("prox_cy", ctypes.c_double), ("prox_cu", ctypes.c_double)]
+                ("prox", ctypes.c_int32), ("prox_cy", ctypes.c_double), ("prox_cu", ctypes.c_double),
+                ("precond_kind", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -130,10 +131,11 @@ def make_problem(nx, ny, nt, alpha, beta, *, T=1.0, dplus=None, dminus=None, ctr
 
 def make_params(gamma, *, delta=1.0, rho=1.0, ya=-math.inf, yb=math.inf, ua=-math.inf, ub=math.inf,
                 krylov_tol=1e-10, krylov_maxit=1000, tol_mode=0, admm_tol=1e-6, admm_maxit=100000,
-                pcg_cold_start=0, prox=0, prox_cy=0.0, prox_cu=0.0):
+                pcg_cold_start=0, prox=0, prox_cy=0.0, prox_cu=0.0, precond_kind=0):
     return Params(gamma=gamma, delta=delta, rho=rho, ya=ya, yb=yb, ua=ua, ub=ub, krylov_tol=krylov_tol,
                   krylov_maxit=krylov_maxit, tol_mode=tol_mode, admm_tol=admm_tol, admm_maxit=admm_maxit,
-                  pcg_cold_start=pcg_cold_start, prox=prox, prox_cy=prox_cy, prox_cu=prox_cu)
+                  pcg_cold_start=pcg_cold_start, prox=prox, prox_cy=prox_cy, prox_cu=prox_cu,
+                  precond_kind=precond_kind)
 
 
 def from_workload(w, precond_fp32=0, **overrides):
@@ -144,7 +146,8 @@ def from_workload(w, precond_fp32=0, **overrides):
     kw = dict(delta=w.delta, rho=w.rho, ya=w.ya, yb=w.yb, ua=w.ua, ub=w.ub, krylov_tol=w.krylov_tol,
               krylov_maxit=w.krylov_maxit, admm_tol=w.admm_tol, admm_maxit=w.admm_maxit,
               tol_mode=getattr(w, "tol_mode", 0), pcg_cold_start=getattr(w, "pcg_cold_start", 0),
-              prox=getattr(w, "prox", 0), prox_cy=getattr(w, "prox_cy", 0.0), prox_cu=getattr(w, "prox_cu", 0.0))
+              prox=getattr(w, "prox", 0), prox_cy=getattr(w, "prox_cy", 0.0), prox_cu=getattr(w, "prox_cu", 0.0),
+              precond_kind=getattr(w, "precond_kind", 0))
     kw.update(overrides)
     return prob, make_params(w.gamma, **kw)
 
