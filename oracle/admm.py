@@ -144,6 +144,82 @@ def pcg(A, M, b, x0, tol, maxit):
     return x, maxit, normr / normb, False
 
 
+def apply_K(d, sc, w, X):
+    """The merged x-step matrix of (3.8) in the scaled variables, applied to
+    X = (y, u, p): symmetric indefinite, with diagonal (1,1), (2,2) blocks."""
+    y, u, p = X
+    return (tcol(sc.My) * y + apply_BT(d, sc, p),
+            tcol(sc.Mu) * u + sc.k_u * p,
+            apply_B(d, sc, y) + sc.k_u * u - (w.delta / w.rho) * p)
+
+
+def apply_Kt_inv(tab, sc, R):
+    """Inverse of the block-diagonal preconditioner K~ of eq. (3.12).  The
+    (1,1), (2,2) blocks M_y, M_u are diagonal and taken exactly.  The third
+    block approximates the Schur complement M_p + B M_y^{-1} B^T of the p block
+    (eliminating y and u from (3.8)); with the scalar blocks a, mbar_p and the
+    circulant C_3(B) that is mbar_p + C_3 C_3^* / a = (mbar_p / a) S~ (or the
+    matching S^ with precond_kind = 1), so its inverse is (a / mbar_p) S~^{-1}."""
+    ry, ru, rp = R
+    return (ry / tcol(sc.My), ru / tcol(sc.Mu), (tab["a"] / tab["mbar_p"]) * apply_precond(tab, rp))
+
+
+def _bdot(X, Y):
+    return float(sum(np.vdot(x, y) for x, y in zip(X, Y)))
+
+
+def minres(A, M, b, x0, tol, maxit):
+    """Preconditioned MINRES (Lanczos in the M^{-1} inner product, Givens QR of
+    the tridiagonal) for symmetric A and symmetric positive definite M, on
+    tuples of fields.  Stops when the M^{-1}-norm of the residual is at most
+    tol times that of b; with tol = 0 it runs exactly maxit iterations.
+    Returns (x, iterations, relative residual, converged)."""
+    zb = M(b)
+    nb = math.sqrt(max(_bdot(zb, b), 0.0))
+    if nb == 0.0:
+        return tuple(np.zeros_like(v) for v in b), 0, 0.0, True
+    x = tuple(v.copy() for v in x0)
+    v = tuple(bb - ax for bb, ax in zip(b, A(x)))
+    z = M(v)
+    g = math.sqrt(max(_bdot(z, v), 0.0))
+    if g <= tol * nb:
+        return x, 0, g / nb, True
+    v_old = tuple(np.zeros_like(f) for f in v)
+    w_old = tuple(np.zeros_like(f) for f in v)
+    w_cur = tuple(np.zeros_like(f) for f in v)
+    g_old = 1.0
+    eta = g
+    c_old = c = 1.0
+    s_old = s = 0.0
+    res = g
+    for k in range(1, maxit + 1):
+        zn = tuple(f / g for f in z)  # z_k normalised
+        q = A(zn)
+        dlt = _bdot(q, zn)
+        # next Lanczos vector (v held unnormalised: v_k = v / g)
+        v_new = tuple(qq - (dlt / g) * vv - (g / g_old) * vo for qq, vv, vo in zip(q, v, v_old))
+        z_new = M(v_new)
+        g_new = math.sqrt(max(_bdot(z_new, v_new), 0.0))
+        # Givens rotation of the new column of the tridiagonal
+        a0 = c * dlt - c_old * s * g
+        a1 = math.hypot(a0, g_new)
+        a2 = s * dlt + c_old * c * g
+        a3 = s_old * g
+        c_new, s_new = a0 / a1, g_new / a1
+        w_new = tuple((zz - a3 * wo - a2 * wc) / a1 for zz, wo, wc in zip(zn, w_old, w_cur))
+        x = tuple(xx + c_new * eta * ww for xx, ww in zip(x, w_new))
+        eta = -s_new * eta
+        res = abs(eta)
+        if tol > 0 and res <= tol * nb:
+            return x, k, res / nb, True
+        v_old, v, z = v, v_new, z_new
+        w_old, w_cur = w_cur, w_new
+        g_old, g = g, g_new
+        c_old, c = c, c_new
+        s_old, s = s, s_new
+    return x, maxit, res / nb, tol > 0 and res <= tol * nb
+
+
 @dataclasses.dataclass
 class AdmmResult:
     y: np.ndarray
@@ -168,7 +244,10 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
     """Run Algorithm 1 on workload `w` from all-zero iterates (or `state`).
 
     iters   -- if given, run exactly this many iterations (no stopping test)
-    solver  -- "pcg" (PCG with S~, warm-started from the previous y) or
+    solver  -- "pcg" (PCG with S~, warm-started from the previous y),
+               "minres" (MINRES on the merged system (3.8) with K~ of
+               eq. (3.12), warm-started from the previous (y, u, p); y is
+               kept and u, p recovered from it as in step 3), or
                "direct" (dense Cholesky of S; tiny grids only)
     """
     d = op.disc_from(w)
@@ -218,14 +297,21 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
         r = sc.k_u * Ru / Mu - h + (delta / rho) * p
         b = Ry - apply_BT(d, sc, r / Mp)
         # 2. normal equations (3.9)
-        if solver == "pcg":
+        if solver in ("pcg", "minres"):
             if getattr(w, "tol_mode", 0) == 1:
                 # Sec. 6.1: 0.05 max{min of the previous iteration's three
                 # residuals, 1e-4}; before the first iteration the minimum is 0
                 prev = 0.0 if j == 1 else min(r_p, r_y, r_u)
                 ktol = 0.05 * max(prev, 1e-4)
-            x0 = np.zeros(shape) if getattr(w, "pcg_cold_start", 0) else y
-            y, it, _, _ = pcg(A, M, b, x0, ktol, w.krylov_maxit)
+            cold = getattr(w, "pcg_cold_start", 0)
+            if solver == "pcg":
+                x0 = np.zeros(shape) if cold else y
+                y, it, _, _ = pcg(A, M, b, x0, ktol, w.krylov_maxit)
+            else:
+                rhs = (Ry, Ru, h - (delta / rho) * p)
+                X0 = tuple(np.zeros(shape) for _ in range(3)) if cold else (y, u, p)
+                (y, _, _), it, _, _ = minres(lambda X: apply_K(d, sc, w, X), lambda R: apply_Kt_inv(tab, sc, R),
+                                             rhs, X0, ktol, w.krylov_maxit)
             pcg_counts.append(it)
         else:
             Lc = Schol
