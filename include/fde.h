@@ -114,6 +114,12 @@ typedef struct {
                              with the same blocks, (C^* + c)(C + c) / mbar_p,
                              c = (a mbar_p)^{1/2} (C the 3-level T. Chan
                              circulant of B, eq. (5.2))                       */
+  int32_t krylov_solver;  /* x-step solver: 0: PCG on the normal equations
+                             (3.9) with S~ (or S^); 1: MINRES on the merged
+                             saddle-point system (3.8) with the block-diagonal
+                             K~ of eq. (3.12) (Sec. 3.3.1), see fde_minres;
+                             krylov_tol, krylov_maxit, tol_mode and
+                             pcg_cold_start apply to either               */
 } fde_admm_params;
 
 typedef struct {
@@ -191,6 +197,24 @@ fde_status fde_precond(fde_ctx* ctx, const double* r, double* z);
  * relative residual.  Synchronises the stream.  FDE_ENOTCONV after
  * krylov_maxit iterations. */
 fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, double* relres);
+
+/* Solve the merged x-step system (3.8) in the scaled variables,
+ *     [ M_y   0     B^T          ] [y]   [b_y]
+ *     [ 0     M_u   k_u I        ] [u] = [b_u]      (B = psi D, k_u = psi s),
+ *     [ B     k_u I -(delta/rho) I] [p]   [b_p]
+ * by preconditioned MINRES (Sec. 3.3.1) with the block-diagonal K~ of
+ * eq. (3.12): M_y and M_u exactly (they are diagonal) and, for the p block,
+ * the circulant approximation of its Schur complement M_p + B M_y^{-1} B^T,
+ * which with the scalar blocks a, mbar_p is (mbar_p / a) S~ (S^ when
+ * precond_kind = 1).  Stops when the K~^{-1}-norm of the residual is at most
+ * krylov_tol times that of b, or after krylov_maxit iterations
+ * (FDE_ENOTCONV).  (y, u, p) hold the initial guess on entry and the solution
+ * on exit; b_* are device fields of the grid's size, none aliasing an unknown.
+ * *iters and *relres (host) receive the count and the final relative residual.
+ * The first call allocates the solver's workspace (22 fields).  Synchronises
+ * the stream. */
+fde_status fde_minres(fde_ctx* ctx, const double* b_y, const double* b_u, const double* b_p, double* y, double* u,
+                      double* p, int* iters, double* relres);
 
 /* Algorithm 1 (2-block ADMM, Sec. 3.1) with the merged x-step: the normal
  * equations solved by fde_krylov's PCG, the z-step as the box projection,

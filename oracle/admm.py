@@ -239,7 +239,7 @@ class AdmmResult:
     e_u: float = 1.0
 
 
-def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
+def admm_solve(w, *, iters: Optional[int] = None, solver: Optional[str] = None,
                krylov_tol: Optional[float] = None, state=None) -> AdmmResult:
     """Run Algorithm 1 on workload `w` from all-zero iterates (or `state`).
 
@@ -250,6 +250,8 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: str = "pcg",
                kept and u, p recovered from it as in step 3), or
                "direct" (dense Cholesky of S; tiny grids only)
     """
+    if solver is None:
+        solver = "minres" if getattr(w, "krylov_solver", 0) == 1 else "pcg"
     d = op.disc_from(w)
     sc = scalars(w, d)
     tab = precond_tables(w, d)

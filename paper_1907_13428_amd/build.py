@@ -22,7 +22,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfde.so")
 
-HIP_SOURCES = ["k_toeplitz.hip", "k_precond.hip", "k_vector.hip", "capi.hip"]
+HIP_SOURCES = ["k_toeplitz.hip", "k_precond.hip", "k_vector.hip", "k_minres.hip", "capi.hip"]
 CPP_SOURCES = ["host_setup.cpp"]
 ARCH = "gfx950"
 

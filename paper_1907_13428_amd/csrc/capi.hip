@@ -110,6 +110,13 @@ struct fde_ctx {
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
   int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
 
+  // MINRES workspace (allocated on first use): Lanczos vectors, preconditioned
+  // vectors and directions, two of each, K z, a scratch field, the p block of
+  // the ADMM right-hand side, five partial-sum arrays and the device scalars
+  bool mr_ready = false;
+  fde::Triple mrV[2]{}, mrZ[2]{}, mrW[2]{}, mrQ{};
+  double *mr_tmp = nullptr, *mr_rhs = nullptr, *mr_part[5] = {}, *ms = nullptr, *h_ms = nullptr;
+
   template <typename T>
   hipError_t alloc(T** p, size_t count) {
     void* v = nullptr;
@@ -489,6 +496,178 @@ fde_status krylov(fde_ctx* c, const double* b, double* x, double tol, int maxit,
 }
 
 // ---------------------------------------------------------------------------
+// MINRES on the merged x-step system (3.8) with K~ of eq. (3.12) (kernels in
+// k_minres.hip).  Same two-phase driving as PCG: minres_begin enqueues the
+// set-up and a first chunk of iterations, minres_continue consumes a readback.
+// The vectors rotate between two buffers each (parity bit), so the launches of
+// an iteration depend on its parity; they are not captured in a graph.
+// ---------------------------------------------------------------------------
+fde_status ensure_minres(fde_ctx* c) {
+  if (c->mr_ready) return FDE_OK;
+  const size_t n = (size_t)c->N;
+  auto tri = [&](fde::Triple* t) -> hipError_t {
+    hipError_t e = c->alloc(&t->y, n);
+    if (e == hipSuccess) e = c->alloc(&t->u, n);
+    if (e == hipSuccess) e = c->alloc(&t->p, n);
+    return e;
+  };
+  for (int i = 0; i < 2; ++i) {
+    HIP_TRY(tri(&c->mrV[i]));
+    HIP_TRY(tri(&c->mrZ[i]));
+    HIP_TRY(tri(&c->mrW[i]));
+  }
+  HIP_TRY(tri(&c->mrQ));
+  HIP_TRY(c->alloc(&c->mr_tmp, n));
+  HIP_TRY(c->alloc(&c->mr_rhs, n));
+  for (auto& p : c->mr_part) HIP_TRY(c->alloc(&p, (size_t)c->maxpart));
+  HIP_TRY(c->alloc(&c->ms, (size_t)fde::kNumMinres));
+  HIP_TRY(hipHostMalloc((void**)&c->h_ms, sizeof(double) * fde::kNumMinres, hipHostMallocDefault));
+  c->mr_ready = true;
+  return FDE_OK;
+}
+
+fde::MinresConsts minres_consts(fde_ctx* c) {
+  fde::MinresConsts k{};
+  k.n = c->N;
+  k.plane = c->nx * c->ny;
+  k.k_u = c->su.k_u;
+  k.dr = c->prm.delta / c->prm.rho;
+  k.My = c->My;
+  k.Mu = c->Mu;
+  return k;
+}
+
+// q = K z with partial sums (z.u, q.u), (z.p, q.p), (z.y, q.y) in mr_part[0..2]
+hipError_t minres_apply_K(fde_ctx* c, fde::Triple z, fde::Triple q, const int* stop, int* nb) {
+  const double psi = c->su.psi;
+  hipError_t e;
+  if ((e = fde::launch_minres_pre(minres_consts(c), z, c->mr_tmp, q.u, c->mr_part[0], c->ints, c->stream, &nb[0])) !=
+      hipSuccess)
+    return e;
+  // q.p = B z.y + (k_u z.u - (delta/rho) z.p)
+  if ((e = apply_op(c, z.y, q.p, false, psi, c->fa, c->fb, nullptr, c->mr_tmp, c->ones, z.p, c->mr_part[1], stop,
+                    &nb[1])) != hipSuccess)
+    return e;
+  // q.y = B^T z.p + M_y z.y
+  return apply_op(c, z.p, q.y, true, psi, c->fa, c->fb, nullptr, z.y, c->My, z.y, c->mr_part[2], stop, &nb[2]);
+}
+
+// z = (a / mbar) S~^{-1} r (the third block of K~^{-1}) with (r, z) partials
+hipError_t minres_precond(fde_ctx* c, double* r, double* z, double* partial, const int* done, int* nb) {
+  fde::PrecondArgs a = pre_args(c, r, z);
+  a.inv_n *= c->su.a * c->su.inv_mbar;
+  a.partial2 = partial;
+  a.done = done;
+  int nb1 = 0;
+  return fde::launch_precond(a, c->fp32, c->stream, &nb1, nb);
+}
+
+struct MinresRun {
+  fde::Triple x{};
+  int maxit = 0;
+  int enqueued = 0;
+  int parity = 0;
+  int iters = 0;
+  double relres = 0;
+  fde_status status = FDE_OK;
+};
+
+hipError_t enqueue_minres_iteration(fde_ctx* c, MinresRun* m) {
+  using namespace fde;
+  const int P = m->parity, O = 1 - P;
+  const int* stop = c->ints + kStop;
+  const MinresConsts k = minres_consts(c);
+  int nb[5] = {0, 0, 0, 0, 0};
+  hipError_t e;
+  if ((e = minres_apply_K(c, c->mrZ[P], c->mrQ, stop, nb)) != hipSuccess) return e;
+  if ((e = launch_minres_scalar(MR_DELTA, c->mr_part[0], nb[0], c->mr_part[1], nb[1], c->mr_part[2], nb[2], c->ms,
+                                c->ints, 0.0, 0, c->stream)) != hipSuccess)
+    return e;
+  // v~_{j+1} over v~_{j-1}; z~_{j+1} = K~^{-1} v~_{j+1}
+  if ((e = launch_minres_vec(MR_LANCZOS, k, c->mrQ, c->mrV[P], c->mrV[O], c->mrZ[O], c->ms, c->mr_part[3], stop,
+                             c->stream, &nb[3])) != hipSuccess)
+    return e;
+  if ((e = minres_precond(c, c->mrV[O].p, c->mrZ[O].p, c->mr_part[4], stop, &nb[4])) != hipSuccess) return e;
+  if ((e = launch_minres_scalar(MR_GIVENS, c->mr_part[3], nb[3], c->mr_part[4], nb[4], nullptr, 0, c->ms, c->ints,
+                                0.0, 0, c->stream)) != hipSuccess)
+    return e;
+  // w_{j+1} over w_{j-1}; x += c_{j+1} eta_j w_{j+1} (runs in the iteration that raises the stop request)
+  if ((e = launch_minres_update(k, c->mrZ[P], c->mrW[P], c->mrW[O], m->x, c->ms, c->ints + kDone, c->stream)) !=
+      hipSuccess)
+    return e;
+  m->parity = O;
+  return hipSuccess;
+}
+
+fde_status minres_post(fde_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->h_ms, c->ms, sizeof(double) * fde::kNumMinres, hipMemcpyDeviceToHost, c->stream));
+  return post_readback(c);
+}
+
+fde_status minres_begin(fde_ctx* c, fde::Triple b, fde::Triple x, double tol, int maxit, bool cold, int predict,
+                        MinresRun* m) {
+  using namespace fde;
+  fde_status st = ensure_minres(c);
+  if (st != FDE_OK) return st;
+  const MinresConsts k = minres_consts(c);
+  *m = MinresRun{};
+  m->x = x;
+  m->maxit = maxit;
+  int nb[5] = {0, 0, 0, 0, 0};
+  // |b| in the K~^{-1} norm; also clears the stop/done flags
+  HIP_TRY(launch_minres_vec(MR_RHS, k, Triple{}, b, Triple{}, c->mrZ[0], nullptr, c->mr_part[3], nullptr, c->stream,
+                            &nb[3]));
+  HIP_TRY(minres_precond(c, b.p, c->mrZ[0].p, c->mr_part[4], nullptr, &nb[4]));
+  HIP_TRY(launch_minres_scalar(MR_NB, c->mr_part[3], nb[3], c->mr_part[4], nb[4], nullptr, 0, c->ms, c->ints, tol,
+                               maxit, c->stream));
+  if (cold)
+    HIP_TRY(launch_minres_vec(MR_ZERO, k, Triple{}, Triple{}, x, Triple{}, nullptr, nullptr, nullptr, c->stream,
+                              nullptr));
+  // v~_1 = b - K x, z~_1 = K~^{-1} v~_1, gamma_1
+  HIP_TRY(minres_apply_K(c, x, c->mrQ, nullptr, nb));
+  HIP_TRY(launch_minres_vec(MR_RESID, k, c->mrQ, b, c->mrV[0], c->mrZ[0], nullptr, c->mr_part[3], nullptr,
+                            c->stream, &nb[3]));
+  HIP_TRY(minres_precond(c, c->mrV[0].p, c->mrZ[0].p, c->mr_part[4], nullptr, &nb[4]));
+  HIP_TRY(launch_minres_scalar(MR_INIT, c->mr_part[3], nb[3], c->mr_part[4], nb[4], nullptr, 0, c->ms, c->ints, tol,
+                               maxit, c->stream));
+  for (Triple* t : {&c->mrV[1], &c->mrW[0], &c->mrW[1]})
+    HIP_TRY(launch_minres_vec(MR_ZERO, k, Triple{}, Triple{}, *t, Triple{}, nullptr, nullptr, nullptr, c->stream,
+                              nullptr));
+  // b = 0: the solution is x = 0
+  HIP_TRY(launch_minres_vec(MR_ZERO, k, Triple{}, Triple{}, x, Triple{}, c->ms, nullptr, nullptr, c->stream, nullptr));
+  const int chunk = predict > 1 ? predict : 2;
+  for (int i = 0; i < chunk && m->enqueued < maxit; ++i, ++m->enqueued) HIP_TRY(enqueue_minres_iteration(c, m));
+  return minres_post(c);
+}
+
+// returns 1 when finished (m->status, iters, relres set), 0 when more work was enqueued
+int minres_continue(fde_ctx* c, MinresRun* m) {
+  using namespace fde;
+  if (!(c->h_ints[kStop] || m->enqueued >= m->maxit)) {
+    for (int i = 0; i < 2 && m->enqueued < m->maxit; ++i, ++m->enqueued) {
+      const hipError_t e = enqueue_minres_iteration(c, m);
+      if (e != hipSuccess) {
+        m->status = (fde_status)fail(FDE_EHIP, std::string("MINRES launch: ") + hipGetErrorString(e));
+        return 1;
+      }
+    }
+    const fde_status st = minres_post(c);
+    if (st != FDE_OK) {
+      m->status = st;
+      return 1;
+    }
+    return 0;
+  }
+  m->iters = c->h_ints[kIter];
+  const double nb = c->h_ms[kMNb];
+  m->relres = nb > 0 ? c->h_ms[kMRes] / nb : 0.0;
+  if (c->h_ints[kConv] < 0) m->status = (fde_status)fail(FDE_ENONFINITE, "non-finite value or breakdown in MINRES");
+  else if (c->h_ints[kConv] == 0) m->status = FDE_ENOTCONV;
+  else m->status = FDE_OK;
+  return 1;
+}
+
+// ---------------------------------------------------------------------------
 // Algorithm 1 as a resumable state machine.  admm_begin enqueues the first
 // iteration; each admm_advance call (made once the posted readback is
 // complete) consumes it and enqueues the next phase:
@@ -507,6 +686,7 @@ struct AdmmRun {
   double prev_min = 0.0;
   double t0 = 0, tp = 0, t_pcg = 0;
   KrylovRun kr;
+  MinresRun mr;
   fde_admm_stats st{};
   fde_status status = FDE_ENOTCONV;
 };
@@ -517,6 +697,21 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   const double psi = s.psi;
   // 1. b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
   HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
+  if (q.krylov_solver == 1) {
+    // MINRES on the merged system (3.8): right-hand side (R_y, R_u, psi g - (delta/rho) p),
+    // R_y = c + (1 - rho) B^T p; warm start from the previous (y, u, p).  The workspace
+    // (mr_rhs among it) exists before the first launch that writes it.
+    const fde_status ws = ensure_minres(c);
+    if (ws != FDE_OK) return ws;
+    HIP_TRY(apply_op(c, R->f.p, c->bvec, true, (1.0 - q.rho) * psi, c->fb, c->fa, nullptr, c->ac, c->ones, nullptr,
+                     nullptr, nullptr, nullptr));
+    HIP_TRY(fde::launch_lincomb(c->N, -q.delta / q.rho, R->f.p, psi, R->f.g, 0.0, nullptr, c->mr_rhs, c->stream));
+    const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(R->prev_min, 1e-4) : q.krylov_tol;
+    R->tp = now();
+    R->phase = PH_PCG;
+    return minres_begin(c, fde::Triple{c->bvec, R->f.Ru, c->mr_rhs}, fde::Triple{R->f.y, R->f.u, R->f.p}, tol,
+                        q.krylov_maxit, q.pcg_cold_start != 0, R->predict, &R->mr);
+  }
   HIP_TRY(apply_op(c, c->av, c->bvec, true, psi, c->fb, c->fa, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr,
                    nullptr));
   // 2. S y = b by PCG, warm-started from the previous y (or from zero)
@@ -582,13 +777,15 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
   const double psi = s.psi;
   switch (R->phase) {
     case PH_PCG: {
-      if (!krylov_continue(c, &R->kr)) return FDE_OK;
+      const bool mr = q.krylov_solver == 1;
+      if (!(mr ? minres_continue(c, &R->mr) : krylov_continue(c, &R->kr))) return FDE_OK;
       R->t_pcg += now() - R->tp;
-      if (R->kr.status < 0) {
+      const fde_status kst = mr ? R->mr.status : R->kr.status;
+      if (kst < 0) {
         R->phase = PH_DONE;
-        return R->kr.status;
+        return kst;
       }
-      const int it = R->kr.iters;
+      const int it = mr ? R->mr.iters : R->kr.iters;
       R->predict = it > 2 ? it - 1 : 2;
       R->st.pcg_total += it;
       R->st.pcg_last = it;
@@ -652,6 +849,9 @@ fde_status free_all(fde_ctx* c) {
   c->allocs.clear();
   if (c->ev) (void)hipEventDestroy(c->ev);
   c->ev = nullptr;
+  if (c->h_ms) (void)hipHostFree(c->h_ms);
+  c->h_ms = nullptr;
+  c->mr_ready = false;
   if (c->h_scal) (void)hipHostFree(c->h_scal);
   if (c->h_ints) (void)hipHostFree(c->h_ints);
   c->h_scal = nullptr;
@@ -952,6 +1152,8 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
     return (fde_status)fail(code, std::string("fde_create: ") + hipGetErrorString(e));
   }
   fde_status us = upload_admm_tables(c);
+  // the MINRES x-step's workspace is allocated here, not inside the solve
+  if (us == FDE_OK && c->prm.krylov_solver == 1) us = ensure_minres(c);
   if (us != FDE_OK) {
     free_all(c);
     delete c;
@@ -1025,7 +1227,9 @@ fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm) {
   ctx->prm = *prm;
   fde::host::set_admm_scalings(prm, &ctx->su);
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  return upload_admm_tables(ctx);
+  const fde_status us = upload_admm_tables(ctx);
+  if (us != FDE_OK || prm->krylov_solver != 1) return us;
+  return ensure_minres(ctx);
 }
 
 fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) {
@@ -1065,6 +1269,31 @@ fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, doub
   if (iters) *iters = it;
   if (relres) *relres = rr;
   return st;
+}
+
+fde_status fde_minres(fde_ctx* ctx, const double* b_y, const double* b_u, const double* b_p, double* y, double* u,
+                      double* p, int* iters, double* relres) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!b_y || !b_u || !b_p || !y || !u || !p) return (fde_status)fail(FDE_EINVAL, "fde_minres: null field");
+  const void* in[3] = {b_y, b_u, b_p};
+  const void* xs[3] = {y, u, p};
+  for (const void* a : in)
+    for (const void* b : xs)
+      if (a == b) return (fde_status)fail(FDE_EINVAL, "fde_minres: right-hand side aliases an unknown");
+  if (y == u || y == p || u == p) return (fde_status)fail(FDE_EINVAL, "fde_minres: aliased unknowns");
+  CHECK_ALIGNED("fde_minres", b_y, b_u, b_p, y, u, p);
+  MinresRun m;
+  fde_status st = minres_begin(ctx, fde::Triple{const_cast<double*>(b_y), const_cast<double*>(b_u),
+                                                const_cast<double*>(b_p)},
+                               fde::Triple{y, u, p}, ctx->prm.krylov_tol, ctx->prm.krylov_maxit, false, 0, &m);
+  if (st != FDE_OK) return st;
+  while (true) {
+    if ((st = wait_readback(ctx)) != FDE_OK) return st;
+    if (minres_continue(ctx, &m)) break;
+  }
+  if (iters) *iters = m.iters;
+  if (relres) *relres = m.relres;
+  return m.status;
 }
 
 fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, double* y, double* u, double* zy,

@@ -139,9 +139,61 @@ enum ScalarSlot {
   kDual,      // dual infeasibility of the final ADMM iterate
   kNumScalars
 };
-enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kNumInts };
+// kStop: MINRES stop request, raised by its Givens step and turned into kDone
+// by the first kernel of the next iteration (the current iteration's update
+// of x must still run)
+enum IntSlot { kDone = 0, kIter, kMaxit, kConv, kStop, kNumInts };
 // slot of (r, z) after iteration `iter` (iteration 0 = the initial residual)
 __host__ __device__ __forceinline__ int rz_slot(int iter) { return (iter & 1) ? kRZ1 : kRZ; }
+
+// ---------------------------------------------------------------------------
+// MINRES on the merged x-step system (3.8) with the block-diagonal K~ of
+// eq. (3.12); a triple is the (y, u, p) blocks of one vector
+// ---------------------------------------------------------------------------
+struct Triple {
+  double *y, *u, *p;
+};
+// device scalars of the MINRES recurrence (a separate small array)
+enum MinresSlot {
+  kMG = 0,   // gamma_j: M^{-1}-norm of the current unnormalised Lanczos vector
+  kMGold,    // gamma_{j-1}
+  kMD,       // delta_j
+  kMC, kMCold, kMS, kMSold,  // Givens cosines / sines of the last two rotations
+  kMEta,     // eta: signed M^{-1}-norm of the residual
+  kMA1, kMA2, kMA3,  // this iteration's rotation coefficients
+  kMX,       // step of x along the new direction (c_{j+1} eta_j)
+  kMZ,       // 1 / gamma_j (normalises z_j in the direction update)
+  kMNb,      // M^{-1}-norm of the right-hand side
+  kMTol,
+  kMRes,     // current residual norm
+  kNumMinres
+};
+enum MinresVecMode { MR_RESID = 0, MR_LANCZOS, MR_RHS, MR_ZERO };
+enum MinresScalarOp { MR_NB = 0, MR_INIT, MR_DELTA, MR_GIVENS };
+struct MinresConsts {
+  int64_t n;
+  int plane;
+  double k_u, dr;            // control coupling; delta / rho
+  const double* My;          // per time slice
+  const double* Mu;
+};
+// tmp = k_u z.u - (delta/rho) z.p ; q.u = M_u z.u + k_u z.p ; partial (z.u, q.u);
+// block 0 also moves the stop request into kDone
+hipError_t launch_minres_pre(const MinresConsts& k, Triple z, double* tmp, double* qu, double* partial, int* ints,
+                             hipStream_t s, int* nb);
+// MR_RESID:   out = b - q           (b passed as v)
+// MR_LANCZOS: out = q / g - (delta / g) v - (g / g_old) out   (out holds v_{j-1} on entry)
+// MR_RHS:     out unused; the M^{-1} blocks of b (passed as v)
+// MR_ZERO:    out = 0 (all three blocks)
+// then z.y = out.y / M_y, z.u = out.u / M_u and partial (z.y, out.y) + (z.u, out.u)
+hipError_t launch_minres_vec(int mode, const MinresConsts& k, Triple q, Triple v, Triple out, Triple z,
+                             const double* ms, double* partial, const int* done, hipStream_t s, int* nb);
+// one block: the scalar step `op` from up to three partial arrays
+hipError_t launch_minres_scalar(int op, const double* p0, int n0, const double* p1, int n1, const double* p2,
+                                int n2, double* ms, int* ints, double tol, int maxit, hipStream_t s);
+// w_new = (z / gamma_j - a3 w_old - a2 w) / a1 into w_old ; x += (c_{j+1} eta) w_new
+hipError_t launch_minres_update(const MinresConsts& k, Triple z, Triple w_old, Triple w, Triple x, const double* ms,
+                                const int* done, hipStream_t s);
 
 // elementwise / reduction kernels
 enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_ALPHA, FIN_CONV, FIN_BETA, FIN_DOT };

@@ -49,6 +49,7 @@ int validate_params(const fde_admm_params* q, std::string* msg) {
   if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
   if (q->prox != 0 && q->prox != 1) { *msg = "prox must be 0 or 1"; return FDE_EINVAL; }
   if (q->precond_kind != 0 && q->precond_kind != 1) { *msg = "precond_kind must be 0 or 1"; return FDE_EINVAL; }
+  if (q->krylov_solver != 0 && q->krylov_solver != 1) { *msg = "krylov_solver must be 0 or 1"; return FDE_EINVAL; }
   if (q->prox) {
     // Algorithm 2 takes its step in (0, 1]; R_y, R_u must not be indefinite
     if (!(q->rho <= 1.0)) { *msg = "prox = 1 (Algorithm 2) needs rho in (0, 1]"; return FDE_EINVAL; }

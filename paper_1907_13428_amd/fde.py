@@ -22,7 +22,7 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
            -4: "FDE_ENONFINITE"}
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
-            "fde_apply_S", "fde_precond", "fde_krylov", "fde_admm_solve", "fde_grad", "fde_time_pass",
+            "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_admm_solve", "fde_grad", "fde_time_pass",
             "fde_autotune", "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error",
             "fde_version"]
 
@@ -50,7 +50,7 @@ class Params(ctypes.Structure):
                 ("krylov_tol", ctypes.c_double), ("krylov_maxit", ctypes.c_int32), ("tol_mode", ctypes.c_int32),
                 ("admm_tol", ctypes.c_double), ("admm_maxit", ctypes.c_int32), ("pcg_cold_start", ctypes.c_int32),
                 ("prox", ctypes.c_int32), ("prox_cy", ctypes.c_double), ("prox_cu", ctypes.c_double),
-                ("precond_kind", ctypes.c_int32)]
+                ("precond_kind", ctypes.c_int32), ("krylov_solver", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.fde_apply_S.argtypes = [P, P, P]
         L.fde_precond.argtypes = [P, P, P]
         L.fde_krylov.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.fde_minres.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
         L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
@@ -131,11 +132,11 @@ def make_problem(nx, ny, nt, alpha, beta, *, T=1.0, dplus=None, dminus=None, ctr
 
 def make_params(gamma, *, delta=1.0, rho=1.0, ya=-math.inf, yb=math.inf, ua=-math.inf, ub=math.inf,
                 krylov_tol=1e-10, krylov_maxit=1000, tol_mode=0, admm_tol=1e-6, admm_maxit=100000,
-                pcg_cold_start=0, prox=0, prox_cy=0.0, prox_cu=0.0, precond_kind=0):
+                pcg_cold_start=0, prox=0, prox_cy=0.0, prox_cu=0.0, precond_kind=0, krylov_solver=0):
     return Params(gamma=gamma, delta=delta, rho=rho, ya=ya, yb=yb, ua=ua, ub=ub, krylov_tol=krylov_tol,
                   krylov_maxit=krylov_maxit, tol_mode=tol_mode, admm_tol=admm_tol, admm_maxit=admm_maxit,
                   pcg_cold_start=pcg_cold_start, prox=prox, prox_cy=prox_cy, prox_cu=prox_cu,
-                  precond_kind=precond_kind)
+                  precond_kind=precond_kind, krylov_solver=krylov_solver)
 
 
 def from_workload(w, precond_fp32=0, **overrides):
@@ -147,7 +148,7 @@ def from_workload(w, precond_fp32=0, **overrides):
               krylov_maxit=w.krylov_maxit, admm_tol=w.admm_tol, admm_maxit=w.admm_maxit,
               tol_mode=getattr(w, "tol_mode", 0), pcg_cold_start=getattr(w, "pcg_cold_start", 0),
               prox=getattr(w, "prox", 0), prox_cy=getattr(w, "prox_cy", 0.0), prox_cu=getattr(w, "prox_cu", 0.0),
-              precond_kind=getattr(w, "precond_kind", 0))
+              precond_kind=getattr(w, "precond_kind", 0), krylov_solver=getattr(w, "krylov_solver", 0))
     kw.update(overrides)
     return prob, make_params(w.gamma, **kw)
 
@@ -240,6 +241,17 @@ class Context:
         it = ctypes.c_int()
         rel = ctypes.c_double()
         st = _check(lib().fde_krylov(self._h, _dptr(b, "b"), _dptr(x, "x"), ctypes.byref(it), ctypes.byref(rel)))
+        return it.value, rel.value, st
+
+    def minres(self, b, x):
+        """MINRES on the merged x-step system: b and x are (y, u, p) tuples of
+        device fields; x holds the initial guess and receives the solution.
+        Returns (iterations, relative residual, status)."""
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        st = _check(lib().fde_minres(self._h, *(_dptr(f, n) for f, n in zip(b, ("b_y", "b_u", "b_p"))),
+                                     *(_dptr(f, n) for f, n in zip(x, ("y", "u", "p"))), ctypes.byref(it),
+                                     ctypes.byref(rel)))
         return it.value, rel.value, st
 
     def admm_solve(self, yhat, g=None, state=None):

@@ -1,0 +1,147 @@
+"""GPU: MINRES on the merged x-step system with the block-diagonal K~ of
+eq. (3.12) (Sec. 3.3.1) against the oracle: single solves through fde_minres
+(converged and at a fixed iteration count), ADMM with the MINRES x-step, and
+the 256^2 x 64 headline grid."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import admm, kkt, precond
+from oracle import operator as op
+from tests.gpu_util import banner, dev, host, rel, zeros
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_1907_13428_amd import fde  # noqa: E402
+
+KEYS = ("y", "u", "zy", "zu", "p", "wy", "wu")
+
+
+def case(kind):
+    if kind == "small":
+        return W.small(ctrl_sign=-1.0, rho=1.3, delta=0.6)
+    if kind == "var_ragged":
+        w = W.small(nx=24, ny=48, nt=6, alpha=1.3, beta=1.7, obj_weights=1)
+        w.dplus = W.coef_sine_x(24, 48)
+        return w
+    if kind == "radix3_matching":
+        return W.small(nx=48, ny=24, nt=12, alpha=1.45, beta=1.55, precond_kind=1)
+    if kind == "caputo_prox":
+        return W.small(nx=16, ny=12, nt=8, alpha_t=0.6, T=0.9, prox=1, rho=0.9)
+    raise KeyError(kind)
+
+
+def oracle_ops(w):
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    tab = precond.precond_tables(w, d)
+    return (lambda X: admm.apply_K(d, sc, w, X)), (lambda R: admm.apply_Kt_inv(tab, sc, R))
+
+
+def fields(w, seed):
+    return tuple(W.random_field(w.shape, seed + i) for i in range(3))
+
+
+@pytest.mark.parametrize("kind", ["small", "var_ragged", "radix3_matching", "caputo_prox"])
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_minres_solve_matches_oracle(kind, fp32):
+    banner("minres solve", kind, "fp32" if fp32 else "fp64")
+    w = case(kind)
+    K, M = oracle_ops(w)
+    b = fields(w, 61)
+    x0 = fields(w, 71)
+    prob, prm = fde.from_workload(w, krylov_tol=1e-10, krylov_maxit=500, precond_fp32=fp32)
+    with fde.Context(prob, prm) as ctx:
+        for start in ("zero", "warm"):
+            xs = tuple(dev(f) for f in x0) if start == "warm" else tuple(zeros(w.shape) for _ in range(3))
+            it, relres, st = ctx.minres(tuple(dev(f) for f in b), xs)
+            got = tuple(host(f) for f in xs)
+            X0 = x0 if start == "warm" else tuple(np.zeros(w.shape) for _ in range(3))
+            ref, itr, relr, conv = admm.minres(K, M, b, X0, 1e-10, 500)
+            assert st == fde.FDE_OK and conv, (start, st)
+            assert abs(it - itr) <= (1 if not fp32 else 2), (start, it, itr)
+            assert relres <= 1e-10
+            for g, r in zip(got, ref):
+                assert rel(g, r) <= 1e-8, (start, rel(g, r))
+
+
+@pytest.mark.parametrize("kind", ["small", "caputo_prox"])
+def test_minres_fixed_iterations_elementwise(kind):
+    """krylov_tol = 0: exactly 7 iterations on both sides, every block
+    element by element."""
+    banner("minres 7 iterations", kind)
+    w = case(kind)
+    K, M = oracle_ops(w)
+    b = fields(w, 81)
+    x0 = fields(w, 91)
+    prob, prm = fde.from_workload(w, krylov_tol=0.0, krylov_maxit=7)
+    with fde.Context(prob, prm) as ctx:
+        xs = tuple(dev(f) for f in x0)
+        it, relres, st = ctx.minres(tuple(dev(f) for f in b), xs)
+        got = tuple(host(f) for f in xs)
+    ref, itr, relr, _ = admm.minres(K, M, b, x0, 0.0, 7)
+    assert st == fde.FDE_ENOTCONV and it == 7 and itr == 7
+    assert abs(relres - relr) <= 1e-9 * relr
+    for g, r in zip(got, ref):
+        assert np.max(np.abs(g - r)) <= 1e-10 * np.max(np.abs(r))
+
+
+def test_minres_zero_rhs_and_guards():
+    banner("minres guards")
+    w = case("small")
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        b = tuple(zeros(w.shape) for _ in range(3))
+        xs = tuple(dev(f) for f in fields(w, 5))
+        it, relres, st = ctx.minres(b, xs)
+        assert st == fde.FDE_OK and it == 0
+        assert all(float(torch.abs(f).max()) == 0.0 for f in xs)
+        with pytest.raises(fde.FdeError) as e:
+            ctx.minres((xs[0], b[1], b[2]), xs)
+        assert e.value.status == fde.FDE_EINVAL
+        # the context's PCG still works after MINRES used the shared flags
+        x = zeros(w.shape)
+        it, relres, st = ctx.krylov(dev(W.random_field(w.shape, 6)), x)
+        assert st == fde.FDE_OK and it > 0
+
+
+@pytest.mark.parametrize("kind", ["small_mixed", "state_trap"])
+def test_admm_with_minres_xstep_matches_oracle(kind):
+    banner("admm minres", kind)
+    if kind == "small_mixed":
+        w = W.small_mixed(krylov_solver=1)
+    else:
+        w = W.small_state(nx=16, ny=12, nt=8, obj_weights=1, krylov_solver=1, rho=1.618, delta=0.4)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        state, stats, status = ctx.admm_solve(dev(w.yhat))
+        got = {k: host(v) for k, v in state.items()}
+    ref = admm.admm_solve(w)
+    assert status == fde.FDE_OK and ref.converged
+    K = stats["admm_iters"]
+    assert abs(K - ref.iters) <= 1
+    assert abs(stats["pcg_total"] - sum(ref.pcg_iters)) <= K
+    if K != ref.iters:
+        ref = admm.admm_solve(w, iters=K)
+    for k in KEYS:
+        assert rel(got[k], getattr(ref, k)) <= 1e-7, k
+    assert kkt.polish(w, got["zy"], got["zu"])["ok"]
+
+
+def test_minres_headline_full_size():
+    """256^2 x 64 in the benchmark's launch configuration: five MINRES
+    iterations from zero, element by element."""
+    banner("full size: minres headline")
+    w = W.headline()
+    K, M = oracle_ops(w)
+    b = fields(w, 101)
+    prob, prm = fde.from_workload(w, krylov_tol=0.0, krylov_maxit=5)
+    with fde.Context(prob, prm) as ctx:
+        ctx.autotune()
+        xs = tuple(zeros(w.shape) for _ in range(3))
+        it, relres, st = ctx.minres(tuple(dev(f) for f in b), xs)
+        got = tuple(host(f) for f in xs)
+    ref, itr, relr, _ = admm.minres(K, M, b, tuple(np.zeros(w.shape) for _ in range(3)), 0.0, 5)
+    assert it == 5 and itr == 5 and abs(relres - relr) <= 1e-9 * relr
+    for g, r in zip(got, ref):
+        assert rel(g, r) <= 1e-10

@@ -54,7 +54,7 @@ def test_problem_validation(field, value, frag):
 @pytest.mark.parametrize("field,value", [("gamma", 0.0), ("delta", -1.0), ("rho", 1.7), ("rho", 0.0),
                                          ("krylov_maxit", 0), ("admm_maxit", 0), ("tol_mode", 5),
                                          ("ya", 1.0), ("ua", math.nan), ("krylov_tol", -1.0),
-                                         ("precond_kind", 2), ("precond_kind", -1)])
+                                         ("precond_kind", 2), ("precond_kind", -1), ("krylov_solver", 2)])
 def test_param_validation(field, value):
     w = W.small()
     prob, prm = fde.from_workload(w)

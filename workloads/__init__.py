@@ -59,6 +59,7 @@ class Workload:
     prox_cy: float = 0.0  # c_y (0: the smallest admissible, max diag J1)
     prox_cu: float = 0.0  # c_u (0: the smallest admissible, max diag J2)
     precond_kind: int = 0  # 0: S~ of eq. (3.10); 1: the matching approximation S^ of eq. (3.11)
+    krylov_solver: int = 0  # 0: PCG on the normal equations; 1: MINRES on the merged system with K~
     yhat: Optional[np.ndarray] = None  # (nt, ny, nx)
     dplus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
     dminus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
