@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--batch-cap", type=int, default=30, help="ADMM iterations per batched instance")
     ap.add_argument("--pass-reps", type=int, default=50, help="launches per pass for the per-pass timing")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's Table 5 protocol")
+    ap.add_argument("--variant-iters", type=int, default=100,
+                    help="ADMM iterations of each preconditioner/ADMM variant on the headline grid")
     return ap.parse_args()
 
 
@@ -144,7 +146,9 @@ def paper_table5_leg(fde, torch):
     Riesz orders 1.3, box on both variables, dynamic Krylov tolerance, PCG from
     zero, ADMM tolerance 1e-4) at the Table 5 grid sizes, FP64 on the GPU,
     beside the printed figures (MATLAB on a CPU).  Each size also runs the
-    generalized ADMM of Sec. 3.3.2 (step 1, R_y = I - J1, R_u = gamma I - J2)."""
+    generalized ADMM of Sec. 3.3.2 (step 1, R_y = I - J1, R_u = gamma I - J2),
+    Algorithm 1 with the matching preconditioner of eq. (3.11), and Algorithm 1
+    with the MINRES x-step (merged system, K~ of eq. (3.12))."""
     import workloads as W
 
     with open(os.path.join(ROOT, "tests", "golden", "paper_table5.json")) as f:
@@ -177,7 +181,9 @@ def paper_table5_leg(fde, torch):
                      "pcg_avg": r["pcg_avg"], "paper_pcg_avg": row["pcg_avg"], "E_L2": r["E_L2"],
                      "paper_E_L2": row["E_L2"], "dual_inf": r["dual_inf"], "paper_dual_inf": row["dual_inf"],
                      "s": r["s"], "paper_s": row["time_s"],
-                     "generalized_admm": run(w.replace(prox=1, rho=1.0), row["n"])})
+                     "generalized_admm": run(w.replace(prox=1, rho=1.0), row["n"]),
+                     "matching_precond": run(w.replace(precond_kind=1), row["n"]),
+                     "minres_xstep": run(w.replace(krylov_solver=1), row["n"])})
     return {"rows": rows, "paper_times": rec["time_note"]}
 
 
@@ -284,6 +290,27 @@ def main():
                     rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))
                 out[tag] = rec
         out["admm_solve_s"] = out["fp64"]["admm_solve_s"]
+
+        # Krylov counts on the variable-coefficient headline grid: S~ (eq. (3.10))
+        # against the matching S^ (eq. (3.11)), under Algorithms 1 and 2, and the
+        # MINRES x-step on the merged system with K~ (eq. (3.12))
+        progress("preconditioner and ADMM variants")
+        var = {}
+        # (the headline's J1 = I, so Algorithm 2 takes c_y = 1.5, c_u = 10 gamma: R_y, R_u nonzero)
+        alg2 = dict(prox=1, prox_cy=1.5, prox_cu=10 * w.gamma)
+        for tag, kw in (("S~_alg1", {}), ("S^_alg1", dict(precond_kind=1)), ("S~_alg2", alg2),
+                        ("S^_alg2", dict(alg2, precond_kind=1)), ("minres_K~_alg1", dict(krylov_solver=1))):
+            prob, prm = fde.from_workload(w.replace(**kw), admm_tol=0.0, admm_maxit=a.variant_iters)
+            with fde.Context(prob, prm) as c3:
+                c3.autotune()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st3, _ = c3.admm_solve(yhat)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            var[tag] = {"admm_iters": st3["admm_iters"], "pcg_avg": round(st3["pcg_total"] / st3["admm_iters"], 2),
+                        "s": round(t, 3), "residuals": [st3["r_p"], st3["r_y"], st3["r_u"]]}
+        out["variants_headline"] = var
 
     # ---- the paper's own test problem and protocol (Table 5 sizes) -----------
     if not a.no_paper:
