@@ -67,3 +67,30 @@ def test_batch_rejects_invalid_instance():
     with pytest.raises(fde.FdeError) as e:
         fde.Batch(probs, list(prms))
     assert "instance 1" in str(e.value)
+
+
+def test_batch_mixed_methods_concurrent_equals_sequential_and_oracle():
+    """Instances that each pick a different method (Algorithm 2, the matching
+    preconditioner, the MINRES x-step, a Caputo time order) run together:
+    concurrent and sequential runs agree bitwise, and every instance follows
+    the oracle."""
+    banner("batch mixed methods")
+    ws = uneven(count=4, seed=11)
+    ws[0] = ws[0].replace(prox=1, prox_cy=1.5, rho=0.9)
+    ws[1] = ws[1].replace(precond_kind=1)
+    ws[2] = ws[2].replace(krylov_solver=1)
+    ws[3] = ws[3].replace(alpha_t=0.6, krylov_solver=1, prox=1)
+    ws = [w.replace(admm_tol=0.0, admm_maxit=20) for w in ws]
+    a, sa, ca = run(ws, True)
+    b, sb, cb = run(ws, False)
+    assert ca == cb
+    for i in range(len(ws)):
+        assert sa[i]["admm_iters"] == sb[i]["admm_iters"] == 20
+        assert sa[i]["pcg_total"] == sb[i]["pcg_total"]
+        for k in a[i]:
+            assert np.array_equal(a[i][k], b[i][k]), (i, k)
+    for i, w in enumerate(ws):
+        ref = admm.admm_solve(w, iters=20)
+        assert abs(sa[i]["pcg_total"] - sum(ref.pcg_iters)) <= 20, (i, sa[i]["pcg_total"], sum(ref.pcg_iters))
+        for k in ("y", "u", "p", "wy", "wu"):
+            assert rel(a[i][k], getattr(ref, k)) <= 1e-7, (i, k)
