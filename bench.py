@@ -30,6 +30,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FP64_PEAK_TF = 78.6  # MI355X FP64 vector peak, TFLOP/s
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
@@ -262,6 +263,23 @@ def main():
     pcg_pass_us = sum(p["us"] for p in passes.values())
     pcg_bytes = sum(p["bytes"] for p in passes.values())
     out["pcg_iteration_passes"] = passes
+    # The line passes are bound by FP64 arithmetic rather than HBM: nominal
+    # FFT flops (5 L log2 L per complex transform of length L = 2n) per launch
+    # against the FP64 vector peak.  Headline: x-lines carry d+(x) (three
+    # transforms per pair of lines); y-lines are constant-coefficient per
+    # column (two per pair).
+    import math
+
+    def fft_flops(n_lines, L, per_pair):
+        return (n_lines / 2) * per_pair * 5.0 * L * math.log2(L)
+
+    alu = {}
+    for name, lines, L, tr in (("xpass_B", w.ny * w.nt, 2 * w.nx, 3), ("xpass_BT", w.ny * w.nt, 2 * w.nx, 3),
+                               ("ypass_B", w.nx * w.nt, 2 * w.ny, 2), ("ypass_BT", w.nx * w.nt, 2 * w.ny, 2)):
+        fl = fft_flops(lines, L, tr)
+        tf = fl / passes[name]["us"] / 1e6
+        alu[name] = {"nominal_fft_flops": fl, "TFLOP/s": round(tf, 1), "frac_fp64_peak": round(tf / FP64_PEAK_TF, 3)}
+    out["line_passes_alu"] = {"peak_TFLOP/s": FP64_PEAK_TF, "passes": alu}
     out["pcg_iteration_model"] = {"us": round(pcg_pass_us, 1), "GB": round(pcg_bytes / 1e9, 4),
                                   "GB/s": round(pcg_bytes / pcg_pass_us / 1e3, 1)}
     ctx.close()
