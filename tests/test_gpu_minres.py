@@ -145,3 +145,25 @@ def test_minres_headline_full_size():
     assert it == 5 and itr == 5 and abs(relres - relr) <= 1e-9 * relr
     for g, r in zip(got, ref):
         assert rel(g, r) <= 1e-10
+
+
+def test_set_params_switches_the_xstep_solver():
+    """A context created for PCG switches to the MINRES x-step through
+    fde_set_params (its workspace is allocated there) and back."""
+    banner("set_params pcg -> minres -> pcg")
+    w = W.small_mixed(nx=12, ny=8, nt=6, admm_tol=0.0, admm_maxit=15)
+    prob, prm = fde.from_workload(w)
+    with fde.Context(prob, prm) as ctx:
+        yhat = dev(w.yhat)
+        s0, st0, _ = ctx.admm_solve(yhat)
+        ctx.set_params(fde.from_workload(w, krylov_solver=1)[1])
+        s1, st1, _ = ctx.admm_solve(yhat)
+        ctx.set_params(fde.from_workload(w)[1])
+        s2, st2, _ = ctx.admm_solve(yhat)
+        got = [{k: host(v) for k, v in s.items()} for s in (s0, s1, s2)]
+    for k in KEYS:
+        assert np.array_equal(got[0][k], got[2][k]), k
+    ref = admm.admm_solve(w.replace(krylov_solver=1), iters=15)
+    assert abs(st1["pcg_total"] - sum(ref.pcg_iters)) <= 15
+    for k in KEYS:
+        assert rel(got[1][k], getattr(ref, k)) <= 1e-7, k
