@@ -786,7 +786,7 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
         return kst;
       }
       const int it = mr ? R->mr.iters : R->kr.iters;
-      R->predict = it > 2 ? it - 1 : 2;
+      R->predict = it > 2 ? it : 2;  // the next x-step usually needs about as many
       R->st.pcg_total += it;
       R->st.pcg_last = it;
       if (it > R->st.pcg_max) R->st.pcg_max = it;
