@@ -21,6 +21,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfde.so")
+EXAMPLE_SRC = os.path.join(PKG, "examples", "c_abi_demo.c")
+EXAMPLE_BIN = os.path.join(PKG, "examples", "c_abi_demo")
 
 HIP_SOURCES = ["k_toeplitz.hip", "k_precond.hip", "k_vector.hip", "k_minres.hip", "capi.hip"]
 CPP_SOURCES = ["host_setup.cpp"]
@@ -71,7 +73,19 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
+    build_example(verbose)
     return LIB
+
+
+def build_example(verbose: bool = False) -> str:
+    """The plain C client of the ABI (examples/c_abi_demo.c), linked against
+    libfde.so and the HIP runtime; it finds libfde.so next to its directory."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc())))
+    _run(["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+          "-I", os.path.join(ROOT, "include"), EXAMPLE_SRC, "-L", PKG, "-lfde", "-L", os.path.join(rocm, "lib"),
+          "-lamdhip64", "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", EXAMPLE_BIN],
+         verbose)
+    return EXAMPLE_BIN
 
 
 def main(argv=None):
