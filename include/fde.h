@@ -236,10 +236,12 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
  * with dD/dalpha = -dL_x/dalpha built from the derivative of the Grünwald
  * recurrence (and of c_a h^-a).  lambda, the multiplier of D y + s u = g:
  *   adjoint_solve = 1: from the adjoint equation D^T lambda = -J1 (y - yhat)
- *     - wy, solved by backward time stepping (the transposed time difference
- *     is upper bidiagonal); each step is a 2-D transposed-Toeplitz solve
- *     (reversed weights) by BiCGSTAB preconditioned with the inverse of the
- *     transposed 2-D T. Chan circulant, to 1e-13 relative residual;
+ *     - wy, solved by backward time stepping (the transposed time matrix is
+ *     upper triangular: bidiagonal for implicit Euler, the Caputo weights of
+ *     eq. (4.5) otherwise, whose history enters each step's right-hand side);
+ *     each step is a 2-D transposed-Toeplitz solve (reversed weights) by
+ *     BiCGSTAB preconditioned with the inverse of the transposed 2-D T. Chan
+ *     circulant, to 1e-13 relative residual;
  *   adjoint_solve = 0: lambda = psi p from the ADMM iterate.
  * wy may be NULL when adjoint_solve = 0.  lambda_out (device field, may be
  * NULL) receives lambda.  Uses the context workspace.  Synchronises.

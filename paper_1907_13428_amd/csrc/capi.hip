@@ -872,12 +872,14 @@ fde_status upload_admm_tables(fde_ctx* c) {
 
 // ---------------------------------------------------------------------------
 // Adjoint state equation D^T lambda = f, f = -J1 (y - yhat) - wy.
-// D^T = E^T - L_x^T - L_y^T with E^T upper bidiagonal in time, so lambda is
-// found by backward time stepping: lambda_{nt} = 0 and for k = nt-1 .. 0
-//     A^T lambda_k = f_k + lambda_{k+1} / h_t,   A = I/h_t - L_x - L_y,
+// D^T = C_t^T (x) I - L_x^T - L_y^T with C_t lower-triangular Toeplitz in time
+// (first column c: implicit Euler (1, -1)/h_t, or the Caputo weights of
+// eq. (4.5) over h_t^alpha_t), so lambda is found by backward time stepping:
+// for k = nt-1 .. 0
+//     A^T lambda_k = f_k - sum_{j > k} c_{j-k} lambda_j,   A = c_0 I - L_x - L_y,
 // a 2-D problem whose transposed Toeplitz products run the weights reversed
 // (G^T for G).  Each step: BiCGSTAB, right-preconditioned by the inverse of
-// the transposed 2-D T. Chan circulant (eigenvalues conj(1/h_t - lx - ly)),
+// the transposed 2-D T. Chan circulant (eigenvalues conj(c_0 - lx - ly)),
 // warm-started from lambda_{k+1}.
 // ---------------------------------------------------------------------------
 struct SliceOps {
@@ -892,7 +894,7 @@ struct SliceOps {
     a.tw = c->twx_emb;
     a.lamA = c->lxTA;
     a.lamB = c->lxTB;
-    a.s_time = 1.0 / c->su.ht;
+    a.s_time = c->su.ct[0];  // diagonal of the time matrix (1/h_t for implicit Euler)
     a.s_sp = -1.0;
     hipError_t e = fde::launch_xpass(a, true, c->var, c->stream, nullptr);
     if (e != hipSuccess) return e;
@@ -937,7 +939,7 @@ fde_status adjoint_solve_impl(fde_ctx* c, const double* yhat, const double* y, c
   SliceOps op{c, plane};
   const double tol = 1e-13;
   const int maxit = 500;
-  const double iht = 1.0 / c->su.ht;
+  const std::vector<double>& ct = c->su.ct;
   double* f = c->bvec;
   HIP_TRY(launch_adjoint_rhs(c->N, (int)plane, c->wts, y, yhat, wy, f, c->stream));
   double *bk = c->By, *r = c->r, *rh = c->q, *p = c->pk, *v = c->fw, *sv = c->ar, *tv = c->Ru, *ph = c->av,
@@ -946,8 +948,15 @@ fde_status adjoint_solve_impl(fde_ctx* c, const double* yhat, const double* y, c
     double* x = lam + (size_t)k * plane;
     const double* fk = f + (size_t)k * plane;
     const double* xn = (k + 1 < c->nt) ? lam + (size_t)(k + 1) * plane : nullptr;
-    // b_k = f_k + lambda_{k+1}/h_t ; x0 = lambda_{k+1}
-    HIP_TRY(launch_lincomb(plane, 1.0, fk, iht, xn, 0.0, nullptr, bk, c->stream));
+    // b_k = f_k - sum_{j > k} c_{j-k} lambda_j (two history terms per launch; zero weights skipped) ;
+    // x0 = lambda_{k+1}
+    HIP_TRY(launch_lincomb(plane, 1.0, fk, xn ? -ct[1] : 0.0, xn, 0.0, nullptr, bk, c->stream));
+    for (int j = k + 2; j < c->nt; j += 2) {
+      const double c0 = -ct[j - k], c1 = (j + 1 < c->nt) ? -ct[j + 1 - k] : 0.0;
+      if (c0 == 0.0 && c1 == 0.0) continue;
+      HIP_TRY(launch_lincomb(plane, 1.0, bk, c0, lam + (size_t)j * plane, c1,
+                             c1 != 0.0 ? lam + (size_t)(j + 1) * plane : nullptr, bk, c->stream));
+    }
     HIP_TRY(launch_lincomb(plane, 1.0, xn, 0.0, nullptr, 0.0, nullptr, x, c->stream));
     HIP_TRY(op.applyAT(x, v));
     HIP_TRY(launch_lincomb(plane, 1.0, bk, -1.0, v, 0.0, nullptr, r, c->stream));
@@ -1136,7 +1145,7 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   chk(c->alloc(&c->part_rz, (size_t)c->maxpart));
   chk(c->alloc(&c->part_max, 3 * (size_t)c->maxpart));
   chk(c->alloc(&c->part_dots, 4 * (size_t)2048));
-  chk(upload_c(c, &c->adj_lt, std::vector<cd>{cd(1.0 / s.ht, 0.0)}));
+  chk(upload_c(c, &c->adj_lt, std::vector<cd>{cd(s.ct[0], 0.0)}));
   chk(upload_tw(c, &c->adj_twt, std::vector<cd>{cd(1.0, 0.0)}, c->fp32));
   chk(c->alloc(&c->scal, fde::kNumScalars));
   chk(c->alloc(&c->ints, fde::kNumInts));
@@ -1433,8 +1442,6 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   double* lam = lambda_out ? lambda_out : c->z;
   if (adjoint_solve) {
     if (!wy) return (fde_status)fail(FDE_EINVAL, "fde_grad: the adjoint solve needs wy");
-    if (c->frac_t)
-      return (fde_status)fail(FDE_EINVAL, "fde_grad: the adjoint solve steps implicit Euler time only (alpha_t = 1)");
     const fde_status st = adjoint_solve_impl(c, yhat, y, wy, lam);
     if (st < 0) return st;
     HIP_TRY(launch_grad_fields(c->N, c->nx * c->ny, c->wts, y, yhat, p, c->su.psi, dyhat, nullptr, c->stream));

@@ -22,9 +22,12 @@ def var_problem(nx=12, ny=8, nt=6):
 
 @pytest.mark.parametrize("var", [False, True])
 @pytest.mark.parametrize("fp32", [0, 1])
-def test_adjoint_solve_matches_sparse_lu(var, fp32):
-    banner("adjoint solve", var, fp32)
-    w = var_problem()
+@pytest.mark.parametrize("alpha_t", [1.0, 0.6])
+def test_adjoint_solve_matches_sparse_lu(var, fp32, alpha_t):
+    """Backward time stepping of D^T lambda = f against a sparse LU of D^T; with
+    a Caputo order the history of later time levels enters every step."""
+    banner("adjoint solve", var, fp32, alpha_t)
+    w = var_problem().replace(alpha_t=alpha_t)
     if not var:
         w.dplus = None
     rng = np.random.Generator(np.random.PCG64(11))

@@ -110,21 +110,32 @@ def test_caputo_graph_replay_matches_plain_launches(monkeypatch):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
-def test_caputo_rejects_the_implicit_euler_only_paths():
-    banner("caputo guards")
-    w = case("small_0.7")
+def test_caputo_adjoint_gradients_and_pass_timer_guard():
+    """With a Caputo order the adjoint solve runs (its lambda satisfies
+    D^T lambda = -J1 (y - yhat) - w_y through the oracle's D^T) and the
+    gradients from it match those from the oracle's lambda; the pass timer,
+    whose pass list is that of implicit Euler, refuses."""
+    banner("caputo adjoint and guards")
+    from oracle import grad
+
+    w = case("var_ragged_0.3")
+    rng = np.random.Generator(np.random.PCG64(12))
+    y = rng.standard_normal(w.shape)
+    wy = rng.standard_normal(w.shape)
     prob, prm = fde.from_workload(w)
     with fde.Context(prob, prm) as ctx:
-        y = zeros(w.shape)
-        with pytest.raises(fde.FdeError) as e:
-            ctx.grad(dev(w.yhat), y, y, y, adjoint_solve=True)
-        assert e.value.status == fde.FDE_EINVAL and "alpha_t" in str(e.value)
+        lam = zeros(w.shape)
+        _, da, db = ctx.grad(dev(w.yhat), dev(y), zeros(w.shape), dev(wy), adjoint_solve=True, lam=lam)
+        got = host(lam)
         with pytest.raises(fde.FdeError) as e:
             ctx.time_pass(0, 5)
         assert e.value.status == fde.FDE_EINVAL
-        # the lambda = psi p gradients remain available
-        _, da, db = ctx.grad(dev(w.yhat), y, y)
-        assert np.isfinite(da) and np.isfinite(db)
+    d = op.disc_from(w)
+    f = -admm.tcol(admm.objective_weights(w)) * (y - w.yhat) - wy
+    assert rel(op.apply_DT(d, got), f) <= 1e-10
+    assert rel(got, grad.adjoint_multiplier(w, y, wy)) <= 1e-10
+    _, ga, gb = grad.gradients(w, y, got)
+    assert abs(da - ga) <= 1e-9 * abs(ga) and abs(db - gb) <= 1e-9 * abs(gb), (da, ga, db, gb)
 
 
 def table5():
