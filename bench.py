@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--batch-cap", type=int, default=30, help="ADMM iterations per batched instance")
     ap.add_argument("--pass-reps", type=int, default=50, help="launches per pass for the per-pass timing")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's Table 5 protocol")
+    ap.add_argument("--precision-iters", type=int, default=20,
+                    help="ADMM iterations of the 1024^2 x 32 precision-form comparison")
     ap.add_argument("--variant-iters", type=int, default=100,
                     help="ADMM iterations of each preconditioner/ADMM variant on the headline grid")
     return ap.parse_args()
@@ -329,6 +331,31 @@ def main():
             var[tag] = {"admm_iters": st3["admm_iters"], "pcg_avg": round(st3["pcg_total"] / st3["admm_iters"], 2),
                         "s": round(t, 3), "residuals": [st3["r_p"], st3["r_y"], st3["r_u"]]}
         out["variants_headline"] = var
+
+    # ---- precision form: 1024^2 x 32, FP32 preconditioner against FP64 ----------
+    if not a.no_full:
+        progress("precision form 1024^2 x 32: FP64 and FP32 preconditioner")
+        wp = W.precision()
+        yp = torch.from_numpy(wp.yhat).to("cuda")
+        rec = {"grid": [wp.nx, wp.ny, wp.nt], "admm_iters": a.precision_iters}
+        sol = {}
+        for tag, fp32 in (("fp64", 0), ("fp32_precond", 1)):
+            prob, prm = fde.from_workload(wp, precond_fp32=fp32, admm_tol=0.0, admm_maxit=a.precision_iters)
+            with fde.Context(prob, prm) as c4:
+                c4.autotune()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s4, st4, _ = c4.admm_solve(yp)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                sol[tag] = (s4["y"].clone(), s4["u"].clone())
+            rec[tag] = {"s": round(t, 3), "pcg_total": st4["pcg_total"],
+                        "pcg_iters_per_s": round(st4["pcg_total"] / t, 1)}
+        (y64, u64), (y32, u32) = sol["fp64"], sol["fp32_precond"]
+        rec["rel_diff_y"] = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
+        rec["rel_diff_u"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+        out["precision_form"] = rec
+        del sol, y64, u64, y32, u32, yp
 
     # ---- the paper's own test problem and protocol (Table 5 sizes) -----------
     if not a.no_paper:
