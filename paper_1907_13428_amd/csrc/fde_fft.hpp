@@ -308,8 +308,4 @@ __device__ __forceinline__ void line_fft(V (&v)[E], LineLds<V> lds, int t, const
   Stages<L, E, 1, SIGN, V>::run(v, lds, t, tw);
 }
 
-// true when a block of `threads` threads running lines of T threads needs
-// block-wide barriers inside line_fft
-template <int L> constexpr bool line_needs_block_sync() { return (L / default_E(L)) > 64; }
-
 }  // namespace fde

@@ -71,7 +71,6 @@ struct LinePassArgs {
 // launchers (return hipError_t of the launch)
 hipError_t launch_xpass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
 hipError_t launch_ypass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);
-bool fft_length_supported(int L);
 int ypass_tile_width(int L, int variant);  // column pairs per block of a variant (0 if unsupported)
 
 // ---------------------------------------------------------------------------
@@ -196,14 +195,13 @@ hipError_t launch_minres_update(const MinresConsts& k, Triple z, Triple w_old, T
                                 const int* done, hipStream_t s);
 
 // elementwise / reduction kernels
-enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_ALPHA, FIN_CONV, FIN_BETA, FIN_DOT };
+// (alpha, the convergence test and beta run fused inside the passes that need them)
+enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_DOT };
 enum VecOp {
   VEC_RESID = 0,    // c = a - b ; partials (c,c) and (a,a)
-  VEC_PUPDATE,      // c = a + beta c
   VEC_COPY,         // c = a
   VEC_DOT,          // partial (a, b)
-  VEC_ZERO_IF_BB0,  // c = 0 when scal[kBB] == 0
-  VEC_SCALE         // c = scal[kDot] * a  (scalar taken from the device slot)
+  VEC_ZERO_IF_BB0   // c = 0 when scal[kBB] == 0
 };
 // FIN_INIT also stores tol2 and maxit in the device slots
 hipError_t launch_pcg_scalar(int op, const double* partial, int n, double* scal, int* ints, hipStream_t s,

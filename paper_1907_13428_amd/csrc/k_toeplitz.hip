@@ -376,19 +376,6 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 #define FDE_FOR_EMBED_LENGTHS(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
-bool fft_length_supported(int L) {
-  switch (L) {
-#define CASE(Lv) case Lv:
-    FDE_FOR_EMBED_LENGTHS(CASE)
-#undef CASE
-    return true;
-    case 4:
-    case 6:
-      return true;
-    default:
-      return false;
-  }
-}
 
 template <int L>
 static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {

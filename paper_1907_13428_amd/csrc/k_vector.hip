@@ -59,32 +59,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalar(int op, const double* par
     case FIN_RZ0:
       scal[kRZ] = s0;
       break;
-    case FIN_ALPHA:
-      scal[kPQ] = s0;
-      scal[kAlpha] = scal[rz_slot(ints[kIter])] / s0;
-      break;
-    case FIN_CONV: {
-      scal[kRR] = s0;
-      const int it = ints[kIter] + 1;
-      ints[kIter] = it;
-      if (s0 != s0) {
-        ints[kDone] = 1;
-        ints[kConv] = -1;
-      } else if (s0 <= scal[kTol2] * scal[kBB]) {
-        ints[kDone] = 1;
-        ints[kConv] = 1;
-      } else if (it >= ints[kMaxit]) {
-        ints[kDone] = 1;
-        ints[kConv] = 0;
-      }
-      break;
-    }
-    case FIN_BETA: {
-      const int it = ints[kIter];
-      scal[kBeta] = s0 / scal[rz_slot(it - 1)];
-      scal[rz_slot(it)] = s0;
-      break;
-    }
     case FIN_DOT:
       scal[kDot] = s0;
       break;
@@ -116,11 +90,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(int op, int64_t n, const double*
         s1 += av * av;
       }
       break;
-    case VEC_PUPDATE: {
-      const double beta = scal[kBeta];
-      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = a[i] + beta * c[i];
-      return;
-    }
     case VEC_COPY:
       for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = a[i];
       return;
@@ -131,11 +100,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(int op, int64_t n, const double*
       if (scal[kBB] != 0.0) return;
       for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = 0.0;
       return;
-    case VEC_SCALE: {
-      const double f = scal[kDot];
-      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = f * a[i];
-      return;
-    }
     default:
       return;
   }
