@@ -421,7 +421,13 @@ struct KrylovRun {
   fde_status status = FDE_OK;
 };
 
-fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int maxit, int predict, KrylovRun* kr) {
+// How krylov_begin forms S x for the initial residual: a full apply (SX_APPLY);
+// x known to be zero (SX_ZERO: S x = 0); or M_p^{-1} B x already in c->fw from the
+// previous ADMM step's recovery pass (SX_BYP: S x = B^T fw + M_y x, half the passes).
+enum SxMode { SX_APPLY = 0, SX_ZERO, SX_BYP };
+
+fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int maxit, int predict, KrylovRun* kr,
+                        int sx = SX_APPLY) {
   using namespace fde;
   const int* done = c->ints + kDone;
   const double tol2 = tol * tol;
@@ -430,7 +436,14 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
   kr->maxit = maxit;
   kr->enqueued = 0;
   // r = b - S x ; (r, r), (b, b) ; tolerance and iteration limit into the device slots
-  HIP_TRY(apply_S(c, x, c->q, nullptr, nullptr, nullptr));
+  if (sx == SX_ZERO) {
+    HIP_TRY(launch_lincomb(c->N, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, c->q, c->stream));
+  } else if (sx == SX_BYP) {
+    HIP_TRY(apply_op(c, c->fw, c->q, true, c->su.psi, c->fa, c->fb, nullptr, x, c->My, nullptr, nullptr, nullptr,
+                     nullptr));
+  } else {
+    HIP_TRY(apply_S(c, x, c->q, nullptr, nullptr, nullptr));
+  }
   HIP_TRY(launch_axpy_dot(VEC_RESID, c->N, b, c->q, c->r, c->scal, c->part_pq, nullptr, c->stream, &nbv));
   HIP_TRY(launch_pcg_scalar(FIN_INIT, c->part_pq, nbv, c->scal, c->ints, c->stream, tol2, maxit));
   HIP_TRY(launch_axpy_dot(VEC_ZERO_IF_BB0, c->N, nullptr, nullptr, x, c->scal, nullptr, nullptr, c->stream,
@@ -683,6 +696,7 @@ struct AdmmRun {
   int j = 0;
   int phase = PH_DONE;
   int predict = 0;
+  bool have_byp = false;  // c->fw holds M_p^{-1} B y for the current y
   double prev_min = 0.0;
   double t0 = 0, tp = 0, t_pcg = 0;
   KrylovRun kr;
@@ -714,12 +728,15 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   }
   HIP_TRY(apply_op(c, c->av, c->bvec, true, psi, c->fb, c->fa, nullptr, c->ac, c->ones, nullptr, nullptr, nullptr,
                    nullptr));
-  // 2. S y = b by PCG, warm-started from the previous y (or from zero)
+  // 2. S y = b by PCG, warm-started from the previous y (or from zero); the initial
+  //    residual reuses M_p^{-1} B y from the previous recovery pass when y is unchanged
   if (q.pcg_cold_start) HIP_TRY(fde::launch_lincomb(c->N, 0.0, nullptr, 0.0, nullptr, 0.0, nullptr, R->f.y, c->stream));
   const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(R->prev_min, 1e-4) : q.krylov_tol;
+  const int sx = q.pcg_cold_start ? SX_ZERO : (R->have_byp ? SX_BYP : SX_APPLY);
+  R->have_byp = false;
   R->tp = now();
   R->phase = PH_PCG;
-  return krylov_begin(c, c->bvec, R->f.y, tol, q.krylov_maxit, R->predict, &R->kr);
+  return krylov_begin(c, c->bvec, R->f.y, tol, q.krylov_maxit, R->predict, &R->kr, sx);
 }
 
 fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* g, double* y, double* u, double* zy,
@@ -749,6 +766,7 @@ fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* 
   k.wts = c->wts;
   k.Mu = c->Mu;
   k.Mp = c->Mp;
+  k.invMp = c->invMp;
   fde::AdmmFields& f = R->f;
   f.yhat = yhat;
   f.g = g;
@@ -794,7 +812,10 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
       HIP_TRY(apply_op(c, R->f.y, c->By, false, psi, c->fa, c->fb, nullptr, nullptr, nullptr, nullptr, nullptr,
                        nullptr, nullptr));
       int nb = 0;
+      // PCG runs keep M_p^{-1} B y in fw for the next x-step's initial residual
+      R->f.byp = mr ? nullptr : c->fw;
       HIP_TRY(fde::launch_admm_update(R->k, R->f, psi, c->stream, &nb));
+      R->have_byp = !mr;
       HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
       R->phase = PH_RES;
       return post_readback(c);

@@ -224,12 +224,14 @@ struct AdmmConsts {
   const double* wts;  // per time slice J1 diagonal
   const double* Mu;   // per time slice
   const double* Mp;
+  const double* invMp;
 };
 struct AdmmFields {
   const double* yhat;
   const double* g;  // may be null
   double *y, *u, *zy, *zu, *p, *wy, *wu;
   double *r, *Ru, *v, *c, *By;
+  double* byp;      // may be null: receives M_p^{-1} B y for the next x-step's initial residual
   double* partial;  // 3 * blocks
 };
 hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s);

@@ -187,7 +187,7 @@ hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi,
 }
 
 // recovery, projection, dual update and the three residual maxima:
-//   p = (By + r)/Mp ; u = (Ru - k_u p)/Mu
+//   p = (By + r)/Mp ; u = (Ru - k_u p)/Mu ; byp = By/Mp (optional, reused by the next x-step)
 //   zy = clip(y + delta wy/e_y) ; zu = clip(u + delta wu/e_u)
 //   wy += (rho/delta) e_y (y - zy) ; wu += (rho/delta) e_u (u - zu)
 //   max |By + k_u u - psi g|, max |y - zy|, max |u - zu|
@@ -210,6 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields
     f.zu[i] = zu;
     f.wy[i] = wy + (rho / delta) * k.e_y * (y - zy);
     f.wu[i] = wu + (rho / delta) * k.e_u * (u - zu);
+    if (f.byp) f.byp[i] = k.invMp[t] * By;
     const double gv = f.g ? f.g[i] : 0.0;
     m0 = nanmax(m0, fabs(By + k.k_u * u - psi * gv));
     m1 = nanmax(m1, fabs(y - zy));
