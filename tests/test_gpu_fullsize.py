@@ -241,3 +241,57 @@ def test_precision_form_subsample_fp32_against_fp64_oracle():
     for fp32, e in errs.items():
         for k, v in e.items():
             assert v <= 1e-7, (fp32, k, v)
+
+
+class _FormulaField:
+    """Read-only view of x[t, j, i] = ((37 m) mod 101) / 101 - 1/2, m the flat
+    index over [nt][ny][nx]: exact in binary floating point, so the GPU and the
+    oracle's row formulas see the same field without a host copy of it."""
+
+    def __init__(self, shape):
+        self.shape = shape
+
+    def __getitem__(self, key):
+        axes = []
+        for k, n in zip(key, self.shape):
+            if isinstance(k, slice):
+                axes.append(np.arange(*k.indices(n)))
+            else:
+                axes.append(np.array([k]))
+        t, j, i = np.meshgrid(*axes, indexing="ij")
+        m = (t.astype(np.int64) * self.shape[1] + j) * self.shape[2] + i
+        out = ((37 * m) % 101) / 101.0 - 0.5
+        return out.reshape([len(a) for a, k in zip(axes, key) if isinstance(k, slice)])
+
+
+def test_maximum_grid_1024_cubed():
+    """The largest supported grid, 1024^3 (2^30 points, 8 GiB per field, byte
+    offsets far beyond 2^31): D and D^T at sampled rows, edges included,
+    against the oracle's row formulas."""
+    banner("full size: maximum grid 1024^3")
+    n = 1024
+    w = W.Workload(name="max_1024", nx=n, ny=n, nt=n, alpha=1.6, beta=1.4, gamma=1e-4, ua=-1.0, ub=1.0)
+    d = op.disc_from(w)
+    pts = sample_points(w, 24, 31)
+    flat = torch.tensor([(t * n + j) * n + i for t, j, i in pts], dtype=torch.int64, device="cuda")
+    prob, prm = fde.from_workload(w)
+    ctx = fde.Context(prob, prm)
+    try:
+        m = torch.arange(w.N, dtype=torch.int64, device="cuda")
+        x = ((37 * m) % 101).to(torch.float64) / 101.0 - 0.5
+        del m
+        x = x.view(w.shape)
+        y = torch.empty_like(x)
+        got = {}
+        for transpose in (False, True):
+            ctx.apply_A(x, y, transpose)
+            got[transpose] = y.view(-1)[flat].cpu().numpy()
+    finally:
+        ctx.close()
+        del x, y
+        torch.cuda.empty_cache()
+    v = _FormulaField(w.shape)
+    for transpose, fn in ((False, op.sampled_D), (True, op.sampled_DT)):
+        ref = fn(d, v, pts)
+        err = float(np.max(np.abs(got[transpose] - ref)))
+        assert err <= 1e-11 * float(np.max(np.abs(ref))), (transpose, err)
