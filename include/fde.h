@@ -211,15 +211,17 @@ fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, doub
  * (FDE_ENOTCONV).  (y, u, p) hold the initial guess on entry and the solution
  * on exit; b_* are device fields of the grid's size, none aliasing an unknown.
  * *iters and *relres (host) receive the count and the final relative residual.
- * The first call allocates the solver's workspace (22 fields).  Synchronises
- * the stream. */
+ * The workspace (22 fields) is allocated at fde_create / fde_set_params when
+ * krylov_solver = 1, else by the first call.  Synchronises the stream. */
 fde_status fde_minres(fde_ctx* ctx, const double* b_y, const double* b_u, const double* b_p, double* y, double* u,
                       double* p, int* iters, double* relres);
 
 /* Algorithm 1 (2-block ADMM, Sec. 3.1) with the merged x-step: the normal
- * equations solved by fde_krylov's PCG, the z-step as the box projection,
+ * equations solved by fde_krylov's PCG (or, with krylov_solver = 1, the
+ * merged system by fde_minres's MINRES), the z-step as the box projection,
  * the dual updates, and the stopping test of Sec. 6.1 on the scaled primal
- * residual and the two copy residuals.  yhat: desired state; g: FDE right-
+ * residual and the two copy residuals.  prox = 1 runs Algorithm 2 instead
+ * (Sec. 3.3.2).  yhat: desired state; g: FDE right-
  * hand side (NULL = 0).  y, u, zy, zu, p, wy, wu are the ADMM iterates
  * (p the scaled multiplier of B y + k_u u = psi g, wy/wu those of the copy
  * constraints): read as the starting point (all zeros for a cold start; a
