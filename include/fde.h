@@ -124,7 +124,8 @@ typedef struct {
 
 typedef struct {
   int32_t admm_iters;     /* iterations performed                                */
-  int32_t pcg_total;      /* PCG iterations summed over all x-steps              */
+  int32_t pcg_total;      /* Krylov (PCG, or MINRES with krylov_solver = 1)
+                             iterations summed over all x-steps              */
   int32_t pcg_last;       /* PCG iterations of the last x-step                   */
   int32_t pcg_max;        /* largest PCG count of one x-step                     */
   double r_p;             /* ||B y + k_u u - psi g||_inf  (scaled constraint)     */
