@@ -167,7 +167,11 @@ fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, 
  * fixes the three variants; see fde_autotune).  Coefficient fields that vary
  * along x only make every y-line constant-coefficient: the y-passes then use
  * per-column multipliers, two transforms per column pair instead of three
- * (FDE_YCOL=0 at create time keeps the general variable-coefficient y-pass). */
+ * (FDE_YCOL=0 at create time keeps the general variable-coefficient y-pass).
+ * The PCG convergence test rides in the preconditioner's y-forward pass, or
+ * runs as its own one-block launch on large grids where every block's sum of
+ * the residual partials would cost more (FDE_CONV_SEPARATE=1 / 0 forces
+ * either; results are identical). */
 fde_status fde_create(const fde_problem* prob, const fde_admm_params* prm, void* stream,
                       fde_ctx** out);
 fde_status fde_destroy(fde_ctx* ctx);

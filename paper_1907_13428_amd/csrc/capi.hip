@@ -109,6 +109,7 @@ struct fde_ctx {
   bool use_graph = true;
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
   int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
+  int conv_sep = -1;  // PCG convergence test: -1 by grid size, 0 fused in the y-forward pass, 1 on its own
 
   // MINRES workspace (allocated on first use): Lanczos vectors, preconditioned
   // vectors and directions, two of each, K z, a scratch field, the p block of
@@ -363,8 +364,17 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   a.scal_w = c->scal;
   a.ints = c->ints;
   if ((e = launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5)) != hipSuccess) return e;
-  a.rr_partial = c->part_rr;  // convergence test inside the y-forward pass
-  a.rr_n = nb1;
+  // The convergence test runs inside the y-forward pass, every block summing
+  // the (r, r) partials; when those redundant sums would read more than a
+  // small launch costs (about 2^21 partial reads, large grids), one block does
+  // the test on its own between the passes.
+  const bool big = (size_t)nb1 * (size_t)c->H * (size_t)c->nt > ((size_t)1 << 25);
+  if (c->conv_sep == 1 || (c->conv_sep < 0 && big)) {
+    if ((e = launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream)) != hipSuccess) return e;
+  } else {
+    a.rr_partial = c->part_rr;
+    a.rr_n = nb1;
+  }
   if ((e = launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5)) != hipSuccess) return e;
   return launch_pupdate(c->N, c->z, c->pk, c->scal, c->ints, c->part_rz, nb5, done, c->stream);
 }
@@ -1072,6 +1082,8 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   c->var = c->su.var;
   c->fp32 = prob->precond_fp32 != 0;
   // FDE_NO_GRAPH=1 launches the PCG iteration kernel by kernel (no HIP graph)
+  // FDE_CONV_SEPARATE=1 / =0 forces the stand-alone / fused PCG convergence test
+  if (const char* cs = std::getenv("FDE_CONV_SEPARATE")) c->conv_sep = (cs[0] == '1') ? 1 : (cs[0] == '0' ? 0 : -1);
   const char* ng = std::getenv("FDE_NO_GRAPH");
   c->use_graph = !(ng && ng[0] == '1');
   // FDE_TILES=a,b,c fixes the column-tile variants (0..2) instead of the default widest tiles

@@ -195,8 +195,10 @@ hipError_t launch_minres_update(const MinresConsts& k, Triple z, Triple w_old, T
                                 const int* done, hipStream_t s);
 
 // elementwise / reduction kernels
-// (alpha, the convergence test and beta run fused inside the passes that need them)
-enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_DOT };
+// (alpha, the convergence test and beta run fused inside the passes that need them;
+// FIN_CONV is the stand-alone convergence test used when the fused form's
+// redundant per-block sums would cost more than one small launch)
+enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_DOT, FIN_CONV };
 enum VecOp {
   VEC_RESID = 0,    // c = a - b ; partials (c,c) and (a,a)
   VEC_COPY,         // c = a

@@ -62,6 +62,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalar(int op, const double* par
     case FIN_DOT:
       scal[kDot] = s0;
       break;
+    case FIN_CONV: {
+      scal[kRR] = s0;
+      const int it = ints[kIter] + 1;
+      ints[kIter] = it;
+      const int conv = (s0 != s0) ? -1 : (s0 <= scal[kTol2] * scal[kBB] ? 1 : 0);
+      if (conv != 0 || it >= ints[kMaxit]) {
+        ints[kConv] = conv;
+        ints[kDone] = 1;
+      }
+      break;
+    }
   }
 }
 

@@ -448,3 +448,28 @@ def test_autotune_then_solve_matches_oracle():
         y = host(state["y"])
     ref = admm.admm_solve(w, iters=stats["admm_iters"])
     assert rel(y, ref.y) <= 1e-7
+
+
+def test_convergence_test_placements_agree(monkeypatch):
+    """The PCG convergence test fused into the preconditioner's y-forward pass
+    and the stand-alone one-block test (used on large grids) stop PCG at the
+    same iteration: Krylov solves and a short ADMM run are bitwise equal, and
+    equal to the oracle."""
+    banner("convergence test: fused vs separate")
+    w = make("ragged_var_24x48x6").replace(ua=-5.0, ub=5.0, admm_tol=0.0, admm_maxit=8)
+    b = W.random_field(w.shape, 44)
+    out = []
+    for sep in ("0", "1"):
+        monkeypatch.setenv("FDE_CONV_SEPARATE", sep)
+        prob, prm = fde.from_workload(w)
+        with fde.Context(prob, prm) as ctx:
+            x = zeros(w.shape)
+            it, relres, st = ctx.krylov(dev(b), x)
+            state, stats, _ = ctx.admm_solve(dev(w.yhat))
+            out.append((it, host(x), {k: host(v) for k, v in state.items()}, stats["pcg_total"]))
+    assert out[0][0] == out[1][0] and np.array_equal(out[0][1], out[1][1])
+    assert out[0][3] == out[1][3]
+    for k in out[0][2]:
+        assert np.array_equal(out[0][2][k], out[1][2][k]), k
+    ref = admm.admm_solve(w, iters=8)
+    assert rel(out[1][2]["y"], ref.y) <= 1e-7
