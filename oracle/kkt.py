@@ -67,6 +67,13 @@ def kkt_residuals(w, y, u, lam, mu_y, mu_u, zy=None, zu=None):
     )
 
 
+def bounds_flat(w):
+    """(ya, yb, ua, ub) as flat arrays over the grid: scalars broadcast, and
+    array-valued bounds (one value per grid point, [nt][ny][nx]) raveled."""
+    return tuple(np.broadcast_to(np.asarray(b, dtype=np.float64), w.shape).ravel()
+                 for b in (w.ya, w.yb, w.ua, w.ub))
+
+
 def polish(w, zy, zu, tol=1e-9, method="auto"):
     """Exact optimum on the active set read off the z-iterates.
 
@@ -94,12 +101,13 @@ def polish(w, zy, zu, tol=1e-9, method="auto"):
         hi_act = np.isfinite(hi) & (z >= hi)
         return lo_act, hi_act
 
-    ylo, yhi = active(zy, w.ya, w.yb)
-    ulo, uhi = active(zu, w.ua, w.ub)
+    ya, yb, ua, ub = bounds_flat(w)
+    ylo, yhi = active(zy, ya, yb)
+    ulo, uhi = active(zu, ua, ub)
     Ay = np.nonzero(ylo | yhi)[0]
     Au = np.nonzero(ulo | uhi)[0]
-    by = np.where(ylo[Ay], w.ya, w.yb) if len(Ay) else np.zeros(0)
-    bu = np.where(ulo[Au], w.ua, w.ub) if len(Au) else np.zeros(0)
+    by = np.where(ylo[Ay], ya[Ay], yb[Ay]) if len(Ay) else np.zeros(0)
+    bu = np.where(ulo[Au], ua[Au], ub[Au]) if len(Au) else np.zeros(0)
     nfree = N - len(Au)
     if method == "reduced" or (method == "auto" and nfree + len(Ay) <= 1500 and w.nx * w.ny <= 4096):
         y, u, lam, my, mu = _polish_reduced(d, J1, w.gamma, s, g, w.yhat.ravel(), Au, bu, Ay, by)
@@ -160,8 +168,9 @@ def _polish_reduced(d, J1, gamma, s, g, yhat, Au, bu, Ay, by):
 
 
 def _finish(w, y, u, lam, my, mu, ylo, yhi, ulo, uhi, tol):
-    feas = (np.all(y >= w.ya - tol) and np.all(y <= w.yb + tol)
-            and np.all(u >= w.ua - tol) and np.all(u <= w.ub + tol))
+    ya, yb, ua, ub = bounds_flat(w)
+    feas = (np.all(y >= ya - tol) and np.all(y <= yb + tol)
+            and np.all(u >= ua - tol) and np.all(u <= ub + tol))
     signs = (np.all(my[ylo] <= tol) and np.all(my[yhi] >= -tol)
              and np.all(mu[ulo] <= tol) and np.all(mu[uhi] >= -tol))
     shp = w.shape
