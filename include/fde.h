@@ -180,6 +180,17 @@ fde_status fde_destroy(fde_ctx* ctx);
  * gamma, delta, rho enter the preconditioner tables, which are rebuilt). */
 fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm);
 
+/* Per-point box bounds (Sec. 3 states the box constraints with bounds that
+ * are functions of space and time; here one value per grid point): ya, yb, ua, ub are device fields of the grid's
+ * size, [nt][ny][nx], +-INFINITY allowed; NULL keeps the scalar bound of
+ * fde_admm_params for that side.  The fields are checked (lower <= upper at
+ * every point, no NaN; FDE_EINVAL otherwise, leaving the previous bounds) and
+ * copied into the context (the caller may free them afterwards); later
+ * fde_set_params calls keep them and are checked against them.  All NULL
+ * restores scalar bounds.  Used by fde_admm_solve (not by fde_batch).
+ * Synchronises the stream. */
+fde_status fde_set_bounds(fde_ctx* ctx, const double* ya, const double* yb, const double* ua, const double* ub);
+
 /* y = D x (transpose = 0) or y = D^T x (transpose = 1), the unscaled
  * constraint matrix of eq. (4.9), by circulant embedding and FFT (Table 1).
  * x and y are device fields and must not alias. */

@@ -110,6 +110,9 @@ struct fde_ctx {
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
   int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
   int conv_sep = -1;  // PCG convergence test: -1 by grid size, 0 fused in the y-forward pass, 1 on its own
+  // per-point box bounds set by fde_set_bounds (context copies; null: the scalar bound)
+  double *bya = nullptr, *byb = nullptr, *bua = nullptr, *bub = nullptr;
+  double *bya_mem = nullptr, *byb_mem = nullptr, *bua_mem = nullptr, *bub_mem = nullptr;
 
   // MINRES workspace (allocated on first use): Lanczos vectors, preconditioned
   // vectors and directions, two of each, K z, a scratch field, the p block of
@@ -777,6 +780,10 @@ fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* 
   k.Mu = c->Mu;
   k.Mp = c->Mp;
   k.invMp = c->invMp;
+  k.lya = c->bya;
+  k.lyb = c->byb;
+  k.lua = c->bua;
+  k.lub = c->bub;
   fde::AdmmFields& f = R->f;
   f.yhat = yhat;
   f.g = g;
@@ -1205,6 +1212,19 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   return FDE_OK;
 }
 
+// lower <= upper at every point (arrays where given, the scalar bounds elsewhere), no NaN
+fde_status check_bounds(fde_ctx* c, const double* ya, const double* yb, const double* ua, const double* ub,
+                        const fde_admm_params& q, const char* who) {
+  int nb = 0;
+  HIP_TRY(fde::launch_bounds_check(c->N, ya, yb, ua, ub, q.ya, q.yb, q.ua, q.ub, c->part_max, c->stream, &nb));
+  HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
+  const fde_status st = sync_scalars(c);
+  if (st != FDE_OK) return st;
+  if (c->h_scal[fde::kResP] != 0.0 || c->h_scal[fde::kResY] != 0.0)
+    return (fde_status)fail(FDE_EINVAL, std::string(who) + ": a lower bound exceeds its upper bound (or is NaN)");
+  return FDE_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1266,6 +1286,11 @@ fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm) {
   std::string msg;
   const int st = fde::host::validate_params(prm, &msg);
   if (st != FDE_OK) return (fde_status)fail(st, msg);
+  if (ctx->bya || ctx->byb || ctx->bua || ctx->bub) {
+    // per-point bounds stay; the new scalar bounds must agree with them
+    const fde_status bs = check_bounds(ctx, ctx->bya, ctx->byb, ctx->bua, ctx->bub, *prm, "fde_set_params");
+    if (bs != FDE_OK) return bs;
+  }
   ctx->prm = *prm;
   fde::host::set_admm_scalings(prm, &ctx->su);
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -1311,6 +1336,33 @@ fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, doub
   if (iters) *iters = it;
   if (relres) *relres = rr;
   return st;
+}
+
+fde_status fde_set_bounds(fde_ctx* ctx, const double* ya, const double* yb, const double* ua, const double* ub) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  CHECK_ALIGNED("fde_set_bounds", ya, yb, ua, ub);
+  fde_ctx* c = ctx;
+  fde_status st = check_bounds(c, ya, yb, ua, ub, c->prm, "fde_set_bounds");
+  if (st != FDE_OK) return st;
+  const size_t bytes = sizeof(double) * (size_t)c->N;
+  const double* src[4] = {ya, yb, ua, ub};
+  double** mem[4] = {&c->bya_mem, &c->byb_mem, &c->bua_mem, &c->bub_mem};
+  double** use[4] = {&c->bya, &c->byb, &c->bua, &c->bub};
+  for (int k = 0; k < 4; ++k) {
+    if (!src[k]) {
+      *use[k] = nullptr;
+      continue;
+    }
+    if (!*mem[k]) {
+      const hipError_t e = c->alloc(mem[k], (size_t)c->N);
+      if (e != hipSuccess)
+        return (fde_status)fail(e == hipErrorOutOfMemory ? FDE_ENOMEM : FDE_EHIP, "fde_set_bounds: allocation");
+    }
+    HIP_TRY(hipMemcpyAsync(*mem[k], src[k], bytes, hipMemcpyDeviceToDevice, c->stream));
+    *use[k] = *mem[k];
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FDE_OK;
 }
 
 fde_status fde_minres(fde_ctx* ctx, const double* b_y, const double* b_u, const double* b_p, double* y, double* u,

@@ -227,6 +227,7 @@ struct AdmmConsts {
   const double* Mu;   // per time slice
   const double* Mp;
   const double* invMp;
+  const double *lya, *lyb, *lua, *lub;  // per-point bounds (null: the scalars above)
 };
 struct AdmmFields {
   const double* yhat;
@@ -240,6 +241,11 @@ hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi,
 hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
                               int* nblocks);
 hipError_t launch_max3_finalize(const double* partial, int nblocks, double* scal, hipStream_t s);
+// per-point bound check: partial[3 b + c] = 1 where a lower bound exceeds its upper one or
+// either is NaN (c = 0: y pair, c = 1: u pair; null arrays take the scalars), else 0
+hipError_t launch_bounds_check(int64_t n, const double* ya, const double* yb, const double* ua, const double* ub,
+                               double sya, double syb, double sua, double sub, double* partial, hipStream_t s,
+                               int* nblocks);
 // dual infeasibility max(|J1 (y - yhat) + btp + e_y wy|, |gamma J1 u + k_u p + e_u wu|) over the
 // grid into scal[kDual]; btp = B^T p.  `partial` holds one slot per block.
 hipError_t launch_dual_inf(const AdmmConsts& k, const AdmmFields& f, double gamma, const double* btp,

@@ -213,8 +213,10 @@ __global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields
     const double u = (f.Ru[i] - k.k_u * p) / k.Mu[t];
     const double y = f.y[i];
     const double wy = f.wy[i], wu = f.wu[i];
-    const double zy = fmin(fmax(y + delta * wy / k.e_y, k.ya), k.yb);
-    const double zu = fmin(fmax(u + delta * wu / k.e_u, k.ua), k.ub);
+    const double ya = k.lya ? k.lya[i] : k.ya, yb = k.lyb ? k.lyb[i] : k.yb;
+    const double ua = k.lua ? k.lua[i] : k.ua, ub = k.lub ? k.lub[i] : k.ub;
+    const double zy = fmin(fmax(y + delta * wy / k.e_y, ya), yb);
+    const double zu = fmin(fmax(u + delta * wu / k.e_u, ua), ub);
     f.p[i] = p;
     f.u[i] = u;
     f.zy[i] = zy;
@@ -260,6 +262,35 @@ __global__ __launch_bounds__(kBlock) void k_max3(const double* partial, int nb, 
 
 hipError_t launch_max3_finalize(const double* partial, int nb, double* scal, hipStream_t s) {
   k_max3<<<1, kBlock, 0, s>>>(partial, nb, scal);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_bounds_check(int64_t n, const double* ya, const double* yb,
+                                                         const double* ua, const double* ub, double sya, double syb,
+                                                         double sua, double sub, double* partial) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double by = 0.0, bu = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    const double a = ya ? ya[i] : sya, b = yb ? yb[i] : syb;
+    const double c = ua ? ua[i] : sua, d = ub ? ub[i] : sub;
+    if (!(a <= b)) by = 1.0;  // also catches NaN
+    if (!(c <= d)) bu = 1.0;
+  }
+  const double ry = block_max<kBlock>(by);
+  const double ru = block_max<kBlock>(bu);
+  if (threadIdx.x == 0) {
+    partial[3 * blockIdx.x + 0] = ry;
+    partial[3 * blockIdx.x + 1] = ru;
+    partial[3 * blockIdx.x + 2] = 0.0;
+  }
+}
+
+hipError_t launch_bounds_check(int64_t n, const double* ya, const double* yb, const double* ua, const double* ub,
+                               double sya, double syb, double sua, double sub, double* partial, hipStream_t s,
+                               int* nblocks) {
+  const int blocks = vec_blocks(n);
+  if (nblocks) *nblocks = blocks;
+  k_bounds_check<<<blocks, kBlock, 0, s>>>(n, ya, yb, ua, ub, sya, syb, sua, sub, partial);
   return hipGetLastError();
 }
 

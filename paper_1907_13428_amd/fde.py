@@ -22,7 +22,7 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
            -4: "FDE_ENONFINITE"}
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
-            "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_admm_solve", "fde_grad", "fde_time_pass",
+            "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_set_bounds", "fde_admm_solve", "fde_grad", "fde_time_pass",
             "fde_autotune", "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error",
             "fde_version"]
 
@@ -85,6 +85,7 @@ def lib():
         L.fde_precond.argtypes = [P, P, P]
         L.fde_krylov.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         L.fde_minres.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.fde_set_bounds.argtypes = [P, P, P, P, P]
         L.fde_admm_solve.argtypes = [P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Stats)]
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
         L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
@@ -253,6 +254,15 @@ class Context:
                                      *(_dptr(f, n) for f, n in zip(x, ("y", "u", "p"))), ctypes.byref(it),
                                      ctypes.byref(rel)))
         return it.value, rel.value, st
+
+    def set_bounds(self, ya=None, yb=None, ua=None, ub=None):
+        """Per-point box bounds (device fields of the grid's shape); None keeps
+        the scalar bound of the parameters for that side."""
+        for t, n in ((ya, "ya"), (yb, "yb"), (ua, "ua"), (ub, "ub")):
+            if t is not None and tuple(t.shape) != tuple(self.shape):
+                raise ValueError(f"{n} must have the grid's shape {tuple(self.shape)}")
+        _check(lib().fde_set_bounds(self._h, _dptr(ya, "ya"), _dptr(yb, "yb"), _dptr(ua, "ua"), _dptr(ub, "ub")),
+               False)
 
     def admm_solve(self, yhat, g=None, state=None):
         """Run ADMM; `state` = dict of y, u, zy, zu, p, wy, wu tensors (zeros if None),
