@@ -46,11 +46,16 @@ def make(kind):
         return W.small(nx=1024, ny=8, nt=4).replace(alpha=1.6, beta=1.4)
     if kind == "tall_8x1024x4":
         return var_fields(W.small(nx=8, ny=1024, nt=4))
+    if kind == "min_4x4x4":  # the smallest supported length on every axis
+        return var_fields(W.small(nx=4, ny=4, nt=4).replace(alpha=1.7, beta=1.3))
+    if kind == "min_mixed_4x6x12":
+        return W.small(nx=4, ny=6, nt=12).replace(alpha=1.2, beta=1.9)
     raise KeyError(kind)
 
 
 OP_CASES = ["small", "headline_24x16x8", "ragged_var_24x48x6", "const_96x12x4", "tiny_var_6x8x4",
-            "laplace_48x24x6", "radix3_192x96x12", "long_1024x8x4", "tall_8x1024x4"]
+            "laplace_48x24x6", "radix3_192x96x12", "long_1024x8x4", "tall_8x1024x4", "min_4x4x4",
+            "min_mixed_4x6x12"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -75,7 +80,8 @@ def test_apply_A(kind, transpose):
     assert rel(got, ref) <= 1e-11, rel(got, ref)
 
 
-@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "ragged_var_24x48x6", "radix3_192x96x12"])
+@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "ragged_var_24x48x6", "radix3_192x96x12",
+                                  "min_4x4x4"])
 def test_apply_S(kind):
     banner("apply_S", kind)
     w = make(kind).replace(rho=1.3, delta=0.6, obj_weights=1)
@@ -109,7 +115,7 @@ def test_precond(kind, fp32):
     assert rel(got, ref) <= tol, rel(got, ref)
 
 
-@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "radix3_192x96x12"])
+@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "radix3_192x96x12", "min_4x4x4", "min_mixed_4x6x12"])
 def test_krylov(kind):
     banner("krylov", kind)
     w = make(kind)
