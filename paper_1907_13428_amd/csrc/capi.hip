@@ -355,12 +355,15 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   int nbS = 0, nb1 = 0, nb5 = 0;
   hipError_t e;
   if ((e = apply_S(c, c->pk, c->q, c->part_pq, done, &nbS)) != hipSuccess) return e;
-  PrecondArgs a = pre_args(c, c->r, c->z);
+  // the preconditioner's output is the next direction p = S~^{-1} r + beta p,
+  // with (r, z) and beta from the spectrum
+  PrecondArgs a = pre_args(c, c->r, c->pk);
   a.q = c->q;
   a.xvec = x;
   a.pvec = c->pk;
   a.partial = c->part_rr;
-  a.partial2 = c->part_rz;
+  a.rzs_partial = c->part_rz;
+  a.pdir = 1;
   a.done = done;
   a.pq_partial = c->part_pq;  // alpha computed inside the x-forward pass
   a.pq_n = nbS;
@@ -378,8 +381,7 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
     a.rr_partial = c->part_rr;
     a.rr_n = nb1;
   }
-  if ((e = launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5)) != hipSuccess) return e;
-  return launch_pupdate(c->N, c->z, c->pk, c->scal, c->ints, c->part_rz, nb5, done, c->stream);
+  return launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5);
 }
 
 void drop_pcg_graph(fde_ctx* c) {
@@ -461,13 +463,14 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
   HIP_TRY(launch_pcg_scalar(FIN_INIT, c->part_pq, nbv, c->scal, c->ints, c->stream, tol2, maxit));
   HIP_TRY(launch_axpy_dot(VEC_ZERO_IF_BB0, c->N, nullptr, nullptr, x, c->scal, nullptr, nullptr, c->stream,
                           nullptr));
-  // z = S~^{-1} r ; p = z ; rz = (r, z)
-  PrecondArgs a = pre_args(c, c->r, c->z);
-  a.partial2 = c->part_rz;
+  // p = z = S~^{-1} r ; rz = (r, z) from the spectrum
+  PrecondArgs a = pre_args(c, c->r, c->pk);
+  a.rzs_partial = c->part_rz;
+  a.pdir = 2;
   a.done = done;
+  a.scal_w = c->scal;
+  a.ints = c->ints;
   HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
-  HIP_TRY(launch_pcg_scalar(FIN_RZ0, c->part_rz, nb5, c->scal, c->ints, c->stream));
-  HIP_TRY(launch_axpy_dot(VEC_COPY, c->N, c->z, nullptr, c->pk, c->scal, nullptr, done, c->stream, nullptr));
   if (c->use_graph) {
     const fde_status st = ensure_pcg_graph(c, x);
     if (st != FDE_OK) return st;
@@ -1182,7 +1185,8 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   c->maxpart = max_partials(c->nx, c->ny, c->nt, s.frac_t);
   chk(c->alloc(&c->part_pq, 2 * (size_t)c->maxpart));
   chk(c->alloc(&c->part_rr, (size_t)c->maxpart));
-  chk(c->alloc(&c->part_rz, (size_t)c->maxpart));
+  // (r, z) partials: one per block of the preconditioner's t-pass (at most H * ny)
+  chk(c->alloc(&c->part_rz, std::max((size_t)c->maxpart, (size_t)c->H * (size_t)c->ny)));
   chk(c->alloc(&c->part_max, 3 * (size_t)c->maxpart));
   chk(c->alloc(&c->part_dots, 4 * (size_t)2048));
   chk(upload_c(c, &c->adj_lt, std::vector<cd>{cd(s.ct[0], 0.0)}));
@@ -1662,6 +1666,7 @@ fde_status fde_autotune(fde_ctx* ctx, int32_t* choices) {
       c->tile_pre_y = v;
       c->tile_pre_t = v;
       PrecondArgs a = pre_args(c, c->r, c->z);
+      a.rzs_partial = c->part_rz;  // the t-pass as in PCG, with its (r, z) partials
       HIP_TRY(time_launches(c, reps, [&]() { return launch_precond_stage(a, c->fp32, 12, c->stream, nullptr, nullptr); },
                             &us));
       if (us < t_best[1]) { t_best[1] = us; best[1] = v; }
@@ -1722,10 +1727,15 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
     HIP_TRY(launch_precond_stage(a0, c->fp32, 1, c->stream, &nb1, nullptr));
     HIP_TRY(hipMemsetAsync(c->part_rr, 0, sizeof(double) * nb1, c->stream));
   }
+  // passes 6 and 7 with the (r, z) partials of the spectrum, as in the solve,
+  // and pass 8 writing the direction p = z + beta p
+  const int nb3 = precond_t_blocks(pre_args(c, c->r, c->z));
+  if (which == 7) HIP_TRY(hipMemsetAsync(c->part_rz, 0, sizeof(double) * nb3, c->stream));
   {
     std::vector<double> h(kNumScalars, 0.0);
     h[kBB] = 1.0;
     h[kTol2] = -1.0;
+    h[kRZ] = h[kRZ1] = 1.0;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpy(c->scal, h.data(), sizeof(double) * kNumScalars, hipMemcpyHostToDevice));
   }
@@ -1738,7 +1748,7 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
     case 3: b = 4 * f8; break;          // read v, acc, extra (= the dot operand); write out
     case 4: b = 6 * f8 + (double)sb; break;  // read r, q, x, p; write r, x, spectrum
     case 5: case 6: case 7: b = 2.0 * (double)sb; break;
-    case 8: b = 2 * f8 + (double)sb; break;  // read spectrum, r; write z
+    case 8: b = 2 * f8 + (double)sb; break;  // read spectrum, p; write p
   }
   auto launch = [&](int rot) -> hipError_t {
     double* const* f = sets[rot & 1];
@@ -1765,7 +1775,12 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
           a.rr_partial = c->part_rr;
           a.rr_n = nb1;
         }
-        if (which == 8) a.partial2 = c->part_rz;
+        if (which == 6 || which == 7) {
+          a.rzs_partial = c->part_rz;
+          a.rzs_n = nb3;
+          a.pdir = 1;
+        }
+        if (which == 8) a.pdir = 1;
         return launch_precond_stage(a, c->fp32, 10 + (which - 3), c->stream, nullptr, nullptr);
       }
     }

@@ -104,13 +104,21 @@ struct PrecondArgs {
   int pq_n;
   const double* rr_partial;  // y-forward: (r, r) = sum(rr_partial[0..rr_n)), convergence test
   int rr_n;
-  double* scal_w;            // device scalars written by block 0 (alpha, pq, rr)
+  double* scal_w;            // device scalars written by block 0 (alpha, pq, rr, rz, beta)
   int* ints;                 // device flags written by block 0 (done, iteration count, convergence)
+  // (r, z) taken from the spectrum (Parseval), so that the x-inverse pass can
+  // write the PCG direction directly:
+  double* rzs_partial;  // t-pass (divide by s): per-block partial sums of (r, z) (nullptr: none)
+  int rzs_n;            // y-inverse: block 0 sums rzs_partial[0..rzs_n) into (r, z) and beta
+  int pdir;             // x-inverse output into z: 0 the preconditioned residual; 1 p = z + beta p
+                        // (z is the direction p, updated in place); 2 p = z (the first direction)
 };
 
 // stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5; 11..15: pass 1..5 alone
 hipError_t launch_precond_stage(const PrecondArgs& a, bool fp32, int stage, hipStream_t s, int* nb_fwd,
                                 int* nb_inv);
+// blocks of the t-pass for the context's tile variant: the count of rzs_partial
+int precond_t_blocks(const PrecondArgs& a);
 inline hipError_t launch_precond(const PrecondArgs& a, bool fp32, hipStream_t s, int* nb_fwd, int* nb_inv) {
   return launch_precond_stage(a, fp32, 0, s, nb_fwd, nb_inv);
 }
@@ -198,10 +206,9 @@ hipError_t launch_minres_update(const MinresConsts& k, Triple z, Triple w_old, T
 // (alpha, the convergence test and beta run fused inside the passes that need them;
 // FIN_CONV is the stand-alone convergence test used when the fused form's
 // redundant per-block sums would cost more than one small launch)
-enum PcgOp { FIN_INIT = 0, FIN_RZ0, FIN_DOT, FIN_CONV };
+enum PcgOp { FIN_INIT = 0, FIN_DOT, FIN_CONV };
 enum VecOp {
   VEC_RESID = 0,    // c = a - b ; partials (c,c) and (a,a)
-  VEC_COPY,         // c = a
   VEC_DOT,          // partial (a, b)
   VEC_ZERO_IF_BB0   // c = 0 when scal[kBB] == 0
 };
@@ -213,8 +220,6 @@ hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, 
                            int* nblocks);
 // p = z + beta p with beta = (r, z)_k / (r, z)_{k-1}, (r, z)_k summed inside
 // from the partials of the z pass (every block in the same order)
-hipError_t launch_pupdate(int64_t n, const double* z, double* p, double* scal, const int* ints,
-                          const double* rz_partial, int rz_n, const int* done, hipStream_t s);
 
 struct AdmmConsts {
   int64_t n;

@@ -15,6 +15,16 @@
 //   3. t: complex FFT along t, divide by s * nx*ny*nt, inverse FFT along t
 //   4. y: inverse complex FFT
 //   5. x: half spectrum -> two real lines (Hermitian completion), fused (r, z)
+//
+// Inside PCG, (r, z) comes from the spectrum instead: with R = DFT(r) over
+// all three axes and z = IDFT(R / s), Parseval gives
+//     (r, z) = sum_k |R_k|^2 / (s_k nx ny nt),
+// and over the half spectrum every column kx other than 0 and nx/2 stands
+// for itself and its conjugate partner -kx (weight 2; s_{-k} = s_k because
+// each 1-D table of a real circulant is conjugate-symmetric).  The t-pass,
+// which holds R_k next to s_k, writes per-block partials; block 0 of the
+// y-inverse pass sums them in a fixed order into (r, z) and beta; the
+// x-inverse pass then writes the direction p = z + beta p itself.
 // TS is the spectrum precision: double, or float for the mixed form.
 #include "fde_fft.hpp"
 #include "fde_internal.hpp"
@@ -184,6 +194,22 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
       if (conv != 0) return;
     }
   }
+  if constexpr (MODE == 0 && SIGN > 0) {
+    if (a.rzs_partial && blockIdx.x == 0) {
+      // (r, z) from the t-pass partials, and beta = (r, z) / (r, z) of the
+      // previous iteration (or the first (r, z) alone) for the x-inverse pass
+      const double rz = block_ordered_sum<NT>(a.rzs_partial, a.rzs_n);
+      if (threadIdx.x == 0) {
+        if (a.pdir == 2) {
+          a.scal_w[kRZ] = rz;
+        } else {
+          const int it = a.ints[kIter];
+          a.scal_w[rz_slot(it)] = rz;
+          a.scal_w[kBeta] = rz / a.scal[rz_slot(it - 1)];
+        }
+      }
+    }
+  }
   const int H = a.H;
   const int tiles = (H + P - 1) / P;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -241,6 +267,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
     const int ky = outer;
     const double2 lx = a.lam_x[kx < H ? kx : 0];
     const double2 ly = a.lam_y[ky];
+    double rz = 0.0;  // this thread's share of (r, z) = sum |R|^2 / (s N)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int kt = t + T * e;
@@ -249,13 +276,25 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
       const double im = a.psi * (lt.y - ly.y - lx.y);
       if constexpr (MODE == 1) {
         const double s = a.a + (re * re + im * im) * a.inv_mbar + a.match2 * re;
-        const TS f = TS(a.inv_n / s);
+        const double fd = a.inv_n / s;
+        const TS f = TS(fd);
+        const double vr = double(v[e].x), vi = double(v[e].y);
+        rz += (vr * vr + vi * vi) * fd;
         v[e] = V{v[e].x * f, v[e].y * f};
       } else {
         // 1 / conj(re + i im) = (re + i im) / (re^2 + im^2)
         const double m = a.inv_n / (re * re + im * im);
         const TS fr = TS(re * m), fi = TS(im * m);
         v[e] = V{v[e].x * fr - v[e].y * fi, v[e].x * fi + v[e].y * fr};
+      }
+    }
+    if constexpr (MODE == 1) {
+      if (a.rzs_partial) {
+        // threads past the tile hold no column; columns 0 and nx/2 count once
+        const bool col = active && kx < H;
+        const double w = (kx == 0 || 2 * kx == a.nx) ? 1.0 : 2.0;
+        const double s = block_sum<NT>(col ? w * rz : 0.0);
+        if (threadIdx.x == 0) a.rzs_partial[blockIdx.x] = s;
       }
     }
     line_fft<L, E, +1>(v, buf, t, tw);
@@ -277,10 +316,12 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// pass 5: half spectrum -> real lines, fused partial sums of (r, z)
+// pass 5: half spectrum -> real lines.  OUT 0: z; 1: z and partial sums of
+// (r, z); 2: the PCG direction p = z + beta p, in place in a.z
 // ---------------------------------------------------------------------------
-template <int L, typename TS, bool DOT>
+template <int L, typename TS, int OUT>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
+  constexpr bool DOT = OUT == 1, UPD = OUT == 2;
   using V = cplx<TS>;
   constexpr int E = default_E(L);
   constexpr int T = L / E;
@@ -313,20 +354,23 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
     v[e] = V{x1.x - x2.y, x1.y + x2.x};  // X1 + i X2
   }
   line_fft<L, E, +1>(v, buf, t, tw);
-  // z out, with (r, z): the r loads of a group of G elements are issued before
-  // the group's stores; a missing line reads line 0 and contributes nothing
+  // z out, with (r, z) or into p: the r (or p) loads of a group of G elements
+  // are issued before the group's stores; a missing line reads line 0 and
+  // contributes nothing
   constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
   const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
+  const double* opnd = DOT ? a.r : a.z;
+  const double beta = UPD ? a.scal[kBeta] : 0.0;
   double rz = 0.0;
 #pragma unroll
   for (int e0 = 0; e0 < E; e0 += G) {
     double r0[G], r1[G];
-    if constexpr (DOT) {
+    if constexpr (DOT || UPD) {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int i = t + T * (e0 + k);
-        r0[k] = a.r[b0 + i];
-        r1[k] = a.r[b1 + i];
+        r0[k] = opnd[b0 + i];
+        r1[k] = opnd[b1 + i];
       }
     }
 #pragma unroll
@@ -334,11 +378,13 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
       const int i = t + T * (e0 + k);
       const double z0 = double(v[e0 + k].x), z1 = double(v[e0 + k].y);
       if (h0) {
-        a.z[b0 + i] = z0;
+        if constexpr (UPD) a.z[b0 + i] = z0 + beta * r0[k];
+        else a.z[b0 + i] = z0;
         if constexpr (DOT) rz += r0[k] * z0;
       }
       if (h1) {
-        a.z[b1 + i] = z1;
+        if constexpr (UPD) a.z[b1 + i] = z1 + beta * r1[k];
+        else a.z[b1 + i] = z1;
         if constexpr (DOT) rz += r1[k] * z1;
       }
     }
@@ -365,8 +411,9 @@ static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) 
     if (a.q) k_pre_xfwd<L, TS, true><<<blocks, kPreThreads, 0, s>>>(a);
     else k_pre_xfwd<L, TS, false><<<blocks, kPreThreads, 0, s>>>(a);
   } else {
-    if (a.partial2) k_pre_xinv<L, TS, true><<<blocks, kPreThreads, 0, s>>>(a);
-    else k_pre_xinv<L, TS, false><<<blocks, kPreThreads, 0, s>>>(a);
+    if (a.pdir == 1) k_pre_xinv<L, TS, 2><<<blocks, kPreThreads, 0, s>>>(a);
+    else if (a.partial2) k_pre_xinv<L, TS, 1><<<blocks, kPreThreads, 0, s>>>(a);
+    else k_pre_xinv<L, TS, 0><<<blocks, kPreThreads, 0, s>>>(a);
   }
   return hipGetLastError();
 }
@@ -396,6 +443,28 @@ static hipError_t pre_t_S(const PrecondArgs& a, hipStream_t s) {
   if (a.div_mode == 1) k_pre_cc<L, TS, 2, -1, S><<<blocks, C::NT, 0, s>>>(a);
   else k_pre_cc<L, TS, 1, -1, S><<<blocks, C::NT, 0, s>>>(a);
   return hipGetLastError();
+}
+
+template <int L, int S> static int t_blocks_S(const PrecondArgs& a) {
+  return ((a.H + CCfg<L, S>::P - 1) / CCfg<L, S>::P) * a.ny;
+}
+
+template <int L> static int t_blocks(const PrecondArgs& a) {
+  switch (a.tile_t) {
+    case 1: return t_blocks_S<L, 1>(a);
+    case 2: return t_blocks_S<L, 2>(a);
+    default: return t_blocks_S<L, 0>(a);
+  }
+}
+
+int precond_t_blocks(const PrecondArgs& a) {
+  switch (a.nt) {
+#define CASE(Lv) case Lv: return t_blocks<Lv>(a);
+    FDE_FOR_DIM_LENGTHS(CASE)
+    CASE(1)
+#undef CASE
+    default: return 0;
+  }
 }
 
 template <int L, typename TS>
@@ -442,7 +511,8 @@ static hipError_t precond_T(const PrecondArgs& a, int stage, hipStream_t s, int*
     }
     if (err != hipSuccess || stage == 1) return err;
   }
-  const PrecondArgs& a2 = a;
+  PrecondArgs a2 = a;
+  a2.rzs_n = precond_t_blocks(a);
   switch (a.ny) {
 #define CASE(Lv) case Lv: err = pre_y<Lv, TS>(a2, -1, s); break;
     FDE_FOR_DIM_LENGTHS(CASE)

@@ -56,9 +56,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalar(int op, const double* par
       }
       break;
     }
-    case FIN_RZ0:
-      scal[kRZ] = s0;
-      break;
     case FIN_DOT:
       scal[kDot] = s0;
       break;
@@ -101,9 +98,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(int op, int64_t n, const double*
         s1 += av * av;
       }
       break;
-    case VEC_COPY:
-      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) c[i] = a[i];
-      return;
     case VEC_DOT:
       for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) s0 += a[i] * b[i];
       break;
@@ -122,21 +116,6 @@ __global__ __launch_bounds__(kBlock) void k_vec(int op, int64_t n, const double*
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, const double* __restrict__ z, double* p,
-                                                    double* scal, const int* ints, const double* rz_partial,
-                                                    int rz_n, const int* done) {
-  if (is_done(done)) return;
-  const int it = ints[kIter];
-  const double rz = block_ordered_sum<kBlock>(rz_partial, rz_n);
-  const double beta = rz / scal[rz_slot(it - 1)];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[rz_slot(it)] = rz;
-    scal[kBeta] = beta;
-  }
-  const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = z[i] + beta * p[i];
-}
-
 static int vec_blocks(int64_t n) {
   int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
   if (b > 2048) b = 2048;
@@ -150,12 +129,6 @@ hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, 
   const int blocks = vec_blocks(n);
   if (nblocks) *nblocks = blocks;
   k_vec<<<blocks, kBlock, 0, s>>>(op, n, a, b, c, scal, partial, done);
-  return hipGetLastError();
-}
-
-hipError_t launch_pupdate(int64_t n, const double* z, double* p, double* scal, const int* ints,
-                          const double* rz_partial, int rz_n, const int* done, hipStream_t s) {
-  k_pupdate<<<vec_blocks(n), kBlock, 0, s>>>(n, z, p, scal, ints, rz_partial, rz_n, done);
   return hipGetLastError();
 }
 
