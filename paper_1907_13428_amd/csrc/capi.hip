@@ -103,8 +103,9 @@ struct fde_ctx {
   // one PCG iteration captured as a HIP graph (re-captured when the
   // solution pointer changes); launched on `stream`
   hipStream_t cap_stream = nullptr;
-  hipGraph_t pcg_graph = nullptr;
-  hipGraphExec_t pcg_exec = nullptr;
+  // PCG iterations captured once: [0] one iteration, [1] kGraphIters in a row
+  hipGraph_t pcg_graph[2] = {nullptr, nullptr};
+  hipGraphExec_t pcg_exec[2] = {nullptr, nullptr};
   const double* pcg_graph_x = nullptr;
   bool use_graph = true;
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
@@ -384,23 +385,29 @@ hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
   return launch_precond_stage(a, c->fp32, 2, c->stream, &nb1, &nb5);
 }
 
+// Iterations per launch of the larger PCG graph.  Consecutive graph launches
+// on a stream are separated by a few microseconds of idle GPU (none between
+// the kernels inside a graph), so chunks of iterations are enqueued mostly
+// as launches of kGraphIters iterations.
+constexpr int kGraphIters = 4;
+
 void drop_pcg_graph(fde_ctx* c) {
-  if (c->pcg_exec) (void)hipGraphExecDestroy(c->pcg_exec);
-  if (c->pcg_graph) (void)hipGraphDestroy(c->pcg_graph);
-  c->pcg_exec = nullptr;
-  c->pcg_graph = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (c->pcg_exec[k]) (void)hipGraphExecDestroy(c->pcg_exec[k]);
+    if (c->pcg_graph[k]) (void)hipGraphDestroy(c->pcg_graph[k]);
+    c->pcg_exec[k] = nullptr;
+    c->pcg_graph[k] = nullptr;
+  }
   c->pcg_graph_x = nullptr;
 }
 
-// capture one PCG iteration on the private capture stream
-fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
-  if (c->pcg_exec && c->pcg_graph_x == x) return FDE_OK;
-  drop_pcg_graph(c);
-  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+// capture iters PCG iterations in a row on the private capture stream
+fde_status capture_pcg_iterations(fde_ctx* c, double* x, int iters, hipGraph_t* gout, hipGraphExec_t* xout) {
   hipStream_t user = c->stream;
   c->stream = c->cap_stream;
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  const hipError_t e = enqueue_pcg_iteration(c, x);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < iters && e == hipSuccess; ++k) e = enqueue_pcg_iteration(c, x);
   hipGraph_t g = nullptr;
   const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   c->stream = user;
@@ -415,10 +422,37 @@ fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
     (void)hipGraphDestroy(g);
     return (fde_status)fail(FDE_EHIP, std::string("PCG graph instantiate: ") + hipGetErrorString(e3));
   }
-  c->pcg_graph = g;
-  c->pcg_exec = ex;
+  *gout = g;
+  *xout = ex;
+  return FDE_OK;
+}
+
+fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
+  if (c->pcg_exec[0] && c->pcg_exec[1] && c->pcg_graph_x == x) return FDE_OK;
+  drop_pcg_graph(c);
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int iters[2] = {1, kGraphIters};
+  for (int k = 0; k < 2; ++k) {
+    const fde_status st = capture_pcg_iterations(c, x, iters[k], &c->pcg_graph[k], &c->pcg_exec[k]);
+    if (st != FDE_OK) {
+      drop_pcg_graph(c);
+      return st;
+    }
+  }
   c->pcg_graph_x = x;
   return FDE_OK;
+}
+
+// enqueue n PCG iterations (graph launches of kGraphIters and of one)
+hipError_t launch_pcg_iterations(fde_ctx* c, double* x, int n) {
+  hipError_t e = hipSuccess;
+  if (!c->use_graph) {
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = enqueue_pcg_iteration(c, x);
+    return e;
+  }
+  for (; n >= kGraphIters && e == hipSuccess; n -= kGraphIters) e = hipGraphLaunch(c->pcg_exec[1], c->stream);
+  for (; n > 0 && e == hipSuccess; --n) e = hipGraphLaunch(c->pcg_exec[0], c->stream);
+  return e;
 }
 
 // PCG on S x = b (x: initial guess in, solution out), in two phases so that
@@ -475,11 +509,9 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
     const fde_status st = ensure_pcg_graph(c, x);
     if (st != FDE_OK) return st;
   }
-  const int chunk = predict > 1 ? predict : 2;
-  for (int k = 0; k < chunk && kr->enqueued < maxit; ++k, ++kr->enqueued) {
-    if (c->use_graph) HIP_TRY(hipGraphLaunch(c->pcg_exec, c->stream));
-    else HIP_TRY(enqueue_pcg_iteration(c, x));
-  }
+  const int chunk = std::min(predict > 1 ? predict : 2, maxit);
+  HIP_TRY(launch_pcg_iterations(c, x, chunk));
+  kr->enqueued = chunk;
   return post_readback(c);
 }
 
@@ -487,12 +519,12 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
 int krylov_continue(fde_ctx* c, KrylovRun* kr) {
   using namespace fde;
   if (!(c->h_ints[kDone] || kr->enqueued >= kr->maxit)) {
-    for (int k = 0; k < 2 && kr->enqueued < kr->maxit; ++k, ++kr->enqueued) {
-      hipError_t e = c->use_graph ? hipGraphLaunch(c->pcg_exec, c->stream) : enqueue_pcg_iteration(c, kr->x);
-      if (e != hipSuccess) {
-        kr->status = (fde_status)fail(FDE_EHIP, std::string("PCG launch: ") + hipGetErrorString(e));
-        return 1;
-      }
+    const int more = std::min(2, kr->maxit - kr->enqueued);
+    const hipError_t e = launch_pcg_iterations(c, kr->x, more);
+    kr->enqueued += more;
+    if (e != hipSuccess) {
+      kr->status = (fde_status)fail(FDE_EHIP, std::string("PCG launch: ") + hipGetErrorString(e));
+      return 1;
     }
     const fde_status st = post_readback(c);
     if (st != FDE_OK) {
