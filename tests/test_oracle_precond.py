@@ -139,3 +139,36 @@ def test_matching_theorem_interval_for_circulant_constraints():
     assert ev.min() >= 0.5 - 1e-12 and ev.max() <= 1.0 + 1e-12
     # and the interval is not trivially [1, 1]: S^ differs from S~
     assert ev.min() < 0.99
+
+
+@pytest.mark.parametrize("nx", [6, 7])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_rz_from_the_half_spectrum(nx, kind):
+    """(r, S~^{-1} r) equals sum |R_k|^2 / (s_k N) over the half spectrum
+    kx = 0..nx/2, with columns other than 0 and nx/2 counted twice: the
+    symbol is even (s_{-k} = s_k) also when the mean coefficients differ
+    (non-symmetric circulants).  This is how the GPU forms (r, z) in PCG."""
+    ny, nt = 5, 4
+    w = W.small(nx=nx, ny=ny, nt=nt).replace(alpha=1.4, beta=1.6, rho=1.3, delta=0.7, gamma=1e-3,
+                                             precond_kind=kind)
+    w.dplus = np.full((ny, nx), 2.0)  # mean d+ = 2, d- = 1: L_x, L_y not symmetric
+    tab = pc.precond_tables(w, op.disc_from(w))
+    s = pc.precond_symbol(tab)
+    neg = s[(-np.arange(nt)) % nt][:, (-np.arange(ny)) % ny][:, :, (-np.arange(nx)) % nx]
+    np.testing.assert_allclose(neg, s, rtol=1e-13)
+    assert not np.allclose(tab["lam_x"].imag, 0.0)  # the circulant really is non-symmetric
+    r = W.random_field(w.shape, 11)
+    direct = float(np.sum(r * pc.apply_precond(tab, r)))
+    R = np.fft.fftn(r)
+    H = nx // 2 + 1
+    wt = np.full(H, 2.0)
+    wt[0] = 1.0
+    if nx % 2 == 0:
+        wt[-1] = 1.0
+    half = float(np.sum(wt * np.abs(R[:, :, :H]) ** 2 / s[:, :, :H])) / r.size
+    assert abs(half - direct) <= 1e-13 * abs(direct)
+    # a weight of 2 on the Nyquist column (or 1 on the others) is visibly wrong
+    bad = wt.copy()
+    bad[-1] = 3.0 - bad[-1]
+    wrong = float(np.sum(bad * np.abs(R[:, :, :H]) ** 2 / s[:, :, :H])) / r.size
+    assert abs(wrong - direct) > 1e-6 * abs(direct)
