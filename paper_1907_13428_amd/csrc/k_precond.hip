@@ -57,6 +57,33 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   const bool h0 = l0 < nlines, h1 = l1 < nlines;
   LineLds<V> buf{lds + g * lpad_size(L), 1};
   const V* tw = reinterpret_cast<const V*>(a.twx);
+
+  // Input lines (with the fused update).  Loads are issued in groups of G
+  // elements before the group's stores (the fields may alias as far as the
+  // compiler knows, so it cannot hoist them itself); a missing line reads
+  // line 0 and is zeroed.  The first group is loaded before the step length
+  // is formed, so that its HBM latency overlaps the ordered sum of partials.
+  constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
+  const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
+  double r0[G], r1[G], q0[G], q1[G], x0[G], x1[G], p0[G], p1[G];
+  auto load_group = [&](int e0) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int i = t + T * (e0 + k);
+      r0[k] = a.r[b0 + i];
+      r1[k] = a.r[b1 + i];
+      if constexpr (FUSE) {
+        q0[k] = a.q[b0 + i];
+        q1[k] = a.q[b1 + i];
+        x0[k] = a.xvec[b0 + i];
+        x1[k] = a.xvec[b1 + i];
+        p0[k] = a.pvec[b0 + i];
+        p1[k] = a.pvec[b1 + i];
+      }
+    }
+  };
+  load_group(0);
+
   double alpha = 0.0;
   if constexpr (FUSE) {
     if (a.pq_partial) {
@@ -72,31 +99,11 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
     }
   }
 
-  // Input lines (with the fused update).  Loads are issued in groups of G
-  // elements before the group's stores (the fields may alias as far as the
-  // compiler knows, so it cannot hoist them itself); a missing line reads
-  // line 0 and is zeroed.
-  constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
-  const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
   V v[E];
   double rr = 0.0;
 #pragma unroll
   for (int e0 = 0; e0 < E; e0 += G) {
-    double r0[G], r1[G], q0[G], q1[G], x0[G], x1[G], p0[G], p1[G];
-#pragma unroll
-    for (int k = 0; k < G; ++k) {
-      const int i = t + T * (e0 + k);
-      r0[k] = a.r[b0 + i];
-      r1[k] = a.r[b1 + i];
-      if constexpr (FUSE) {
-        q0[k] = a.q[b0 + i];
-        q1[k] = a.q[b1 + i];
-        x0[k] = a.xvec[b0 + i];
-        x1[k] = a.xvec[b1 + i];
-        p0[k] = a.pvec[b0 + i];
-        p1[k] = a.pvec[b1 + i];
-      }
-    }
+    if (e0 > 0) load_group(e0);
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int i = t + T * (e0 + k);
@@ -172,6 +179,44 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
   __shared__ V lds[lpad_size(L) * RS];
   if (a.done && *a.done) return;
+  const int H = a.H;
+  const int tiles = (H + P - 1) / P;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int outer = tile / tiles;  // MODE 0: time slice; MODE 1, 2: ky row
+  const int k0 = (tile % tiles) * P;
+  // element (line index i, column c) address in the spectrum
+  size_t base, stride;
+  if (MODE == 0) {
+    base = (size_t)outer * a.ny * H;
+    stride = H;
+  } else {
+    base = (size_t)outer * H;
+    stride = (size_t)a.ny * H;
+  }
+  V* spec = reinterpret_cast<V*>(a.spec);
+  const V* tw = reinterpret_cast<const V*>(MODE == 0 ? a.twy : a.twt);
+  const int tid = threadIdx.x;
+  const bool active = tid < P * T;
+  const int g = active ? tid / T : P, t = tid % T;
+  LineLds<V> buf{lds + g, RS};
+
+  // tile load: all loads of a thread are issued before the first LDS store
+  // (and before the fused scalar steps below, whose sums then overlap them);
+  // elements outside the tile or the plane read the tile's first element
+  // (always inside) and are zeroed after the load
+  constexpr int NE = L * P;
+  constexpr int KL = (NE + NT - 1) / NT;
+  auto elem = [&](int k, bool& ok) -> size_t {
+    const int idx = tid + k * NT;
+    const int row = idx / P, c = idx % P;
+    ok = idx < NE && k0 + c < H;
+    return base + (ok ? row * stride + c : 0) + k0;
+  };
+  V lv[KL];
+  bool ok[KL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) lv[k] = spec[elem(k, ok[k])];
+
   if constexpr (MODE == 0 && SIGN < 0) {
     if (a.rr_partial) {
       // PCG convergence test on the recursively updated residual (fused).
@@ -210,48 +255,10 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
       }
     }
   }
-  const int H = a.H;
-  const int tiles = (H + P - 1) / P;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int outer = tile / tiles;  // MODE 0: time slice; MODE 1, 2: ky row
-  const int k0 = (tile % tiles) * P;
-  // element (line index i, column c) address in the spectrum
-  size_t base, stride;
-  if (MODE == 0) {
-    base = (size_t)outer * a.ny * H;
-    stride = H;
-  } else {
-    base = (size_t)outer * H;
-    stride = (size_t)a.ny * H;
-  }
-  V* spec = reinterpret_cast<V*>(a.spec);
-  const V* tw = reinterpret_cast<const V*>(MODE == 0 ? a.twy : a.twt);
-  const int tid = threadIdx.x;
-  const bool active = tid < P * T;
-  const int g = active ? tid / T : P, t = tid % T;
-  LineLds<V> buf{lds + g, RS};
-
-  // tile load: all loads of a thread are issued before the first LDS store;
-  // elements outside the tile or the plane read the tile's first element
-  // (always inside) and are zeroed after the load
-  constexpr int NE = L * P;
-  constexpr int KL = (NE + NT - 1) / NT;
-  auto elem = [&](int k, bool& ok) -> size_t {
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
     const int idx = tid + k * NT;
-    const int row = idx / P, c = idx % P;
-    ok = idx < NE && k0 + c < H;
-    return base + (ok ? row * stride + c : 0) + k0;
-  };
-  {
-    V lv[KL];
-    bool ok[KL];
-#pragma unroll
-    for (int k = 0; k < KL; ++k) lv[k] = spec[elem(k, ok[k])];
-#pragma unroll
-    for (int k = 0; k < KL; ++k) {
-      const int idx = tid + k * NT;
-      if (idx < NE) lds[lpad(idx / P) * RS + idx % P] = ok[k] ? lv[k] : V{TS(0), TS(0)};
-    }
+    if (idx < NE) lds[lpad(idx / P) * RS + idx % P] = ok[k] ? lv[k] : V{TS(0), TS(0)};
   }
   __syncthreads();
   V v[E];
