@@ -745,6 +745,7 @@ struct AdmmRun {
   int phase = PH_DONE;
   int predict = 0;
   bool have_byp = false;  // c->fw holds M_p^{-1} B y for the current y
+  bool have_rhs = false;  // the update pass already wrote this iteration's Ru, r, v, c
   double prev_min = 0.0;
   double t0 = 0, tp = 0, t_pcg = 0;
   KrylovRun kr;
@@ -758,7 +759,8 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   const fde_admm_params& q = c->prm;
   const double psi = s.psi;
   // 1. b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
-  HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
+  if (!R->have_rhs) HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
+  R->have_rhs = false;
   if (q.krylov_solver == 1) {
     // MINRES on the merged system (3.8): right-hand side (R_y, R_u, psi g - (delta/rho) p),
     // R_y = c + (1 - rho) B^T p; warm start from the previous (y, u, p).  The workspace
@@ -866,8 +868,11 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
       int nb = 0;
       // PCG runs keep M_p^{-1} B y in fw for the next x-step's initial residual
       R->f.byp = mr ? nullptr : c->fw;
-      HIP_TRY(fde::launch_admm_update(R->k, R->f, psi, c->stream, &nb));
+      // (with the next iteration's right-hand side pieces, computed from the
+      // new iterate while it is in registers)
+      HIP_TRY(fde::launch_admm_update(R->k, R->f, psi, c->stream, &nb, true));
       R->have_byp = !mr;
+      R->have_rhs = true;
       HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
       R->phase = PH_RES;
       return post_readback(c);

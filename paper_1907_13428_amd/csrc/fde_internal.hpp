@@ -243,8 +243,9 @@ struct AdmmFields {
   double* partial;  // 3 * blocks
 };
 hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s);
+// next_rhs: also write the next iteration's right-hand side pieces (Ru, r, v, c)
 hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
-                              int* nblocks);
+                              int* nblocks, bool next_rhs);
 hipError_t launch_max3_finalize(const double* partial, int nblocks, double* scal, hipStream_t s);
 // per-point bound check: partial[3 b + c] = 1 where a lower bound exceeds its upper one or
 // either is NaN (c = 0: y pair, c = 1: u pair; null arrays take the scalars), else 0

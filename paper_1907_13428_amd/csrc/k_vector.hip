@@ -142,26 +142,34 @@ hipError_t launch_axpy_dot(int op, int64_t n, const double* a, const double* b, 
 //   c  = rho (J1 yhat - e_y wy + e_y^2 zy / delta)
 // and under Algorithm 2 (Sec. 3.3.2) rho R_u u and rho R_y y, at the previous
 // iterate, join Ru and c.
+// the x-step right-hand side pieces at point i (time level t) from the
+// iterate (p, wu, zu, wy, zy, u, y) held in registers
+__device__ __forceinline__ void rhs_point(const AdmmConsts& k, const AdmmFields& f, double psi, int64_t i, int t,
+                                          double p, double wu, double zu, double wy, double zy, double u,
+                                          double y) {
+  const double rho = k.rho, delta = k.delta;
+  double xu = -k.e_u * wu + k.e_u * k.e_u * zu / delta;
+  double xy = k.wts[t] * f.yhat[i] - k.e_y * wy + k.e_y * k.e_y * zy / delta;
+  if (k.prox) {
+    // Algorithm 2: R_u u^j and R_y y^j at the previous iterate
+    xu += (k.cu - k.gamma * k.wts[t]) * u;
+    xy += (k.cy - k.wts[t]) * y;
+  }
+  const double Ru = rho * xu + (1.0 - rho) * k.k_u * p;
+  const double gv = f.g ? f.g[i] : 0.0;
+  const double r = k.k_u * Ru / k.Mu[t] - psi * gv + (delta / rho) * p;
+  f.Ru[i] = Ru;
+  f.r[i] = r;
+  f.v[i] = (1.0 - rho) * p - r / k.Mp[t];
+  f.c[i] = rho * xy;
+}
+
 __global__ __launch_bounds__(kBlock) void k_admm_rhs(AdmmConsts k, AdmmFields f, double psi) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  const double rho = k.rho, delta = k.delta;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < k.n; i += stride) {
     const int t = (int)(i / k.plane);
-    const double p = f.p[i];
-    double xu = -k.e_u * f.wu[i] + k.e_u * k.e_u * f.zu[i] / delta;
-    double xy = k.wts[t] * f.yhat[i] - k.e_y * f.wy[i] + k.e_y * k.e_y * f.zy[i] / delta;
-    if (k.prox) {
-      // Algorithm 2: R_u u^j and R_y y^j at the previous iterate
-      xu += (k.cu - k.gamma * k.wts[t]) * f.u[i];
-      xy += (k.cy - k.wts[t]) * f.y[i];
-    }
-    const double Ru = rho * xu + (1.0 - rho) * k.k_u * p;
-    const double gv = f.g ? f.g[i] : 0.0;
-    const double r = k.k_u * Ru / k.Mu[t] - psi * gv + (delta / rho) * p;
-    f.Ru[i] = Ru;
-    f.r[i] = r;
-    f.v[i] = (1.0 - rho) * p - r / k.Mp[t];
-    f.c[i] = rho * xy;
+    const double u = k.prox ? f.u[i] : 0.0, y = k.prox ? f.y[i] : 0.0;
+    rhs_point(k, f, psi, i, t, f.p[i], f.wu[i], f.zu[i], f.wy[i], f.zy[i], u, y);
   }
 }
 
@@ -175,6 +183,10 @@ hipError_t launch_admm_rhs(const AdmmConsts& k, const AdmmFields& f, double psi,
 //   zy = clip(y + delta wy/e_y) ; zu = clip(u + delta wu/e_u)
 //   wy += (rho/delta) e_y (y - zy) ; wu += (rho/delta) e_u (u - zu)
 //   max |By + k_u u - psi g|, max |y - zy|, max |u - zu|
+// With NEXT, the right-hand side pieces of the next iteration follow from the
+// new iterate in registers (they replace Ru and r after their last use here;
+// unused if the run stops at this iteration).
+template <bool NEXT>
 __global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields f, double psi) {
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   const double rho = k.rho, delta = k.delta;
@@ -190,13 +202,16 @@ __global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields
     const double ua = k.lua ? k.lua[i] : k.ua, ub = k.lub ? k.lub[i] : k.ub;
     const double zy = fmin(fmax(y + delta * wy / k.e_y, ya), yb);
     const double zu = fmin(fmax(u + delta * wu / k.e_u, ua), ub);
+    const double wy1 = wy + (rho / delta) * k.e_y * (y - zy);
+    const double wu1 = wu + (rho / delta) * k.e_u * (u - zu);
     f.p[i] = p;
     f.u[i] = u;
     f.zy[i] = zy;
     f.zu[i] = zu;
-    f.wy[i] = wy + (rho / delta) * k.e_y * (y - zy);
-    f.wu[i] = wu + (rho / delta) * k.e_u * (u - zu);
+    f.wy[i] = wy1;
+    f.wu[i] = wu1;
     if (f.byp) f.byp[i] = k.invMp[t] * By;
+    if constexpr (NEXT) rhs_point(k, f, psi, i, t, p, wu1, zu, wy1, zy, u, y);
     const double gv = f.g ? f.g[i] : 0.0;
     m0 = nanmax(m0, fabs(By + k.k_u * u - psi * gv));
     m1 = nanmax(m1, fabs(y - zy));
@@ -213,10 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_admm_update(AdmmConsts k, AdmmFields
 }
 
 hipError_t launch_admm_update(const AdmmConsts& k, const AdmmFields& f, double psi, hipStream_t s,
-                              int* nblocks) {
+                              int* nblocks, bool next_rhs) {
   const int blocks = vec_blocks(k.n);
   if (nblocks) *nblocks = blocks;
-  k_admm_update<<<blocks, kBlock, 0, s>>>(k, f, psi);
+  if (next_rhs) k_admm_update<true><<<blocks, kBlock, 0, s>>>(k, f, psi);
+  else k_admm_update<false><<<blocks, kBlock, 0, s>>>(k, f, psi);
   return hipGetLastError();
 }
 
