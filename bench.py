@@ -217,7 +217,7 @@ def batched_leg(fde, torch, cap):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark measures one GPU; runs on several GPUs are not supported",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
