@@ -278,9 +278,11 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
  * context's workspace (contents are overwritten).  which:
  *   0 x-pass of B (time difference fused)   1 y-pass of B (scaled by M_p^-1)
  *   2 x-pass of B^T                          3 y-pass of B^T (+ M_y v, (v, Sv))
- *   4 preconditioner x-forward (fused r -= alpha q, x += alpha p, (r, r))
- *   5 preconditioner y-forward   6 t-forward/divide/t-inverse
- *   7 preconditioner y-inverse   8 x-inverse (fused (r, z))
+ *   4 preconditioner x-forward (fused alpha, r -= alpha q, x += alpha p, (r, r))
+ *   5 preconditioner y-forward (fused convergence test)
+ *   6 t-forward/divide/t-inverse (fused (r, z) partials from the spectrum)
+ *   7 preconditioner y-inverse (fused (r, z) and beta)
+ *   8 x-inverse writing the direction p = z + beta p
  * Synchronises the stream. */
 fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes);
 
