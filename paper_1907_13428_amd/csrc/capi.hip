@@ -1373,7 +1373,9 @@ fde_status fde_krylov(fde_ctx* ctx, const double* b, double* x, int* iters, doub
   CHECK_ALIGNED("fde_krylov", b, x);
   int it = 0;
   double rr = 0;
-  const fde_status st = krylov(ctx, b, x, ctx->prm.krylov_tol, ctx->prm.krylov_maxit, &it, &rr, 0);
+  // a first chunk of two 4-iteration graph launches; iterations past
+  // convergence return at once (device done flag)
+  const fde_status st = krylov(ctx, b, x, ctx->prm.krylov_tol, ctx->prm.krylov_maxit, &it, &rr, 8);
   if (iters) *iters = it;
   if (relres) *relres = rr;
   return st;

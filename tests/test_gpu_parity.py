@@ -194,14 +194,24 @@ def test_time_pass_then_solve():
         assert rel(admm.apply_S(d, sc, host(x)), b) <= 1e-9
 
 
-def test_krylov_maxit_reports_not_converged():
-    banner("krylov maxit")
-    w = make("small").replace(krylov_maxit=2, krylov_tol=1e-14)
-    prob, prm = fde.from_workload(w)
-    with fde.Context(prob, prm) as ctx:
-        x = zeros(w.shape)
-        it, relres, st = ctx.krylov(dev(W.random_field(w.shape, 2)), x)
-    assert st == fde.FDE_ENOTCONV and it == 2
+@pytest.mark.parametrize("maxit", [2, 7, 13])
+def test_krylov_maxit_reports_not_converged(maxit, monkeypatch):
+    """The iteration limit stops PCG after exactly maxit iterations, whether a
+    chunk is launched as graphs of four iterations, of one, or both (7, 13),
+    and the iterate equals that of plain launches bitwise."""
+    banner("krylov maxit", maxit)
+    w = make("small").replace(krylov_maxit=maxit, krylov_tol=1e-30)
+    b = W.random_field(w.shape, 2)
+    out = []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("FDE_NO_GRAPH", mode)
+        prob, prm = fde.from_workload(w)
+        with fde.Context(prob, prm) as ctx:
+            x = zeros(w.shape)
+            it, relres, st = ctx.krylov(dev(b), x)
+            out.append(host(x))
+        assert st == fde.FDE_ENOTCONV and it == maxit, (mode, st, it)
+    assert np.array_equal(out[0], out[1])
 
 
 def _admm_compare(w, fp32=0, tol=1e-7):
