@@ -1335,6 +1335,9 @@ fde_status fde_set_params(fde_ctx* ctx, const fde_admm_params* prm) {
   ctx->prm = *prm;
   fde::host::set_admm_scalings(prm, &ctx->su);
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  // the captured PCG iterations hold the preconditioner's scalars (a, 1/mbar_p,
+  // the matching term) by value: recapture on the next solve
+  drop_pcg_graph(ctx);
   const fde_status us = upload_admm_tables(ctx);
   if (us != FDE_OK || prm->krylov_solver != 1) return us;
   return ensure_minres(ctx);
