@@ -196,6 +196,20 @@ fde_status fde_set_bounds(fde_ctx* ctx, const double* ya, const double* yb, cons
  * x and y are device fields and must not alias. */
 fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fde_apply_A with its intermediate fields in a fixed static device array
+ * (32 MiB = 2^22 doubles per GPU, held until the process ends) instead of the
+ * context's workspace.  Calls no hipMalloc/hipFree.  Grids needing more than
+ * 2^22 doubles of workspace (N points with implicit Euler, 2N with a
+ * fractional time order) are rejected with FDE_EINVAL; the context's device
+ * must be current (FDE_EINVAL otherwise).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams, or different host
+ * threads) race and must be ordered by the caller.  Nothing in the array needs
+ * to start at zero (each call writes it before reading).  Same arguments and
+ * results as fde_apply_A. */
+fde_status fde_apply_A_noalloc(fde_ctx* ctx, const double* x, double* y, int transpose);
+
 /* y = S x with S = M_y + B^T M_p^{-1} B the normal-equations matrix of the
  * ADMM x-step (eq. (3.9), in the psi-scaled form B = psi D).  No aliasing. */
 fde_status fde_apply_S(fde_ctx* ctx, const double* x, double* y);

@@ -61,11 +61,42 @@ double now() {
 }
 }  // namespace
 
+// Workspace of fde_apply_A_noalloc: a fixed device array, one copy per GPU
+// that loads the library, held until the process ends; the library never
+// allocates or frees it.  Host code must not pass `scratch` itself to a
+// kernel (in host code the name is a stand-in, not a device address): it uses
+// the per-device address obtained once with hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = size_t(1) << 22;  // 32 MiB per GPU
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up on the first call
+// made with that device current.
+int scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FDE_EINVAL, "device index out of range for the static workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FDE_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return FDE_OK;
+}
+}  // namespace
+
 struct fde_ctx {
   fde_problem prob{};
   fde_admm_params prm{};
   fde::host::Setup su;
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device current at fde_create
   int nx = 0, ny = 0, nt = 0, H = 0;
   int64_t N = 0;
   bool var = false, fp32 = false;
@@ -1121,6 +1152,10 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   c->prob.dminus = nullptr;
   c->prm = *prm;
   c->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return (fde_status)fail(FDE_EHIP, "fde_create: no current HIP device");
+  }
   c->nx = prob->nx;
   c->ny = prob->ny;
   c->nt = prob->nt;
@@ -1350,6 +1385,29 @@ fde_status fde_apply_A(fde_ctx* ctx, const double* x, double* y, int transpose) 
   const bool tr = transpose != 0;
   HIP_TRY(apply_op(ctx, x, y, tr, 1.0, ctx->fa, ctx->fb, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                    nullptr));
+  return FDE_OK;
+}
+
+fde_status fde_apply_A_noalloc(fde_ctx* ctx, const double* x, double* y, int transpose) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (!x || !y || x == y) return (fde_status)fail(FDE_EINVAL, "fde_apply_A_noalloc: null or aliased fields");
+  CHECK_ALIGNED("fde_apply_A_noalloc", x, y);
+  // intermediate fields: one (implicit Euler) or two (fractional time order) of N points
+  const size_t need = (ctx->frac_t ? 2 : 1) * (size_t)ctx->N;
+  if (need > kScratchDoubles)
+    return (fde_status)fail(FDE_EINVAL, "fde_apply_A_noalloc: the grid needs " + std::to_string(need) +
+                                            " doubles of workspace; the static workspace holds " +
+                                            std::to_string(kScratchDoubles));
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != ctx->device)
+    return (fde_status)fail(FDE_EINVAL, "fde_apply_A_noalloc: the context's device must be current");
+  double* ws = nullptr;
+  const int st = scratch_address(dev, &ws);
+  if (st != FDE_OK) return (fde_status)st;
+  // N is even (nx is), so ws + N keeps the 16-byte alignment of the pair accesses
+  HIP_TRY(apply_op(ctx, x, y, transpose != 0, 1.0, ws, ws + ctx->N, nullptr, nullptr, nullptr, nullptr, nullptr,
+                   nullptr, nullptr));
   return FDE_OK;
 }
 

@@ -22,6 +22,7 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
            -4: "FDE_ENONFINITE"}
 
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
+            "fde_apply_A_noalloc",
             "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_set_bounds", "fde_admm_solve", "fde_grad", "fde_time_pass",
             "fde_autotune", "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error",
             "fde_version"]
@@ -81,6 +82,7 @@ def lib():
         L.fde_destroy.argtypes = [P]
         L.fde_set_params.argtypes = [P, ctypes.POINTER(Params)]
         L.fde_apply_A.argtypes = [P, P, P, ctypes.c_int]
+        L.fde_apply_A_noalloc.argtypes = [P, P, P, ctypes.c_int]
         L.fde_apply_S.argtypes = [P, P, P]
         L.fde_precond.argtypes = [P, P, P]
         L.fde_krylov.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
@@ -228,6 +230,11 @@ class Context:
     # -- entry points ----------------------------------------------------
     def apply_A(self, x, y, transpose=False):
         _check(lib().fde_apply_A(self._h, _dptr(x, "x"), _dptr(y, "y"), int(transpose)), False)
+        return y
+
+    def apply_A_noalloc(self, x, y, transpose=False):
+        """apply_A with the library's static per-GPU workspace (no device allocation)."""
+        _check(lib().fde_apply_A_noalloc(self._h, _dptr(x, "x"), _dptr(y, "y"), int(transpose)), False)
         return y
 
     def apply_S(self, x, y):
