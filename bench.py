@@ -52,6 +52,15 @@ def parse():
                     help="ADMM iterations of the 1024^2 x 32 precision-form comparison")
     ap.add_argument("--variant-iters", type=int, default=100,
                     help="ADMM iterations of each preconditioner/ADMM variant on the headline grid")
+    ap.add_argument("--diff-iters", type=int, default=30,
+                    help="ADMM iterations of the 512^2 x 32 differentiation form before its backward pass")
+    ap.add_argument("--admm-sweep", action="store_true",
+                    help="only sweep the ADMM settings (psi scaling of the u copies, delta, rho) on the headline "
+                         "grid: iterations and time to the 1e-4 and 1e-6 stopping tests; prints one JSON line")
+    ap.add_argument("--sweep-cap", type=int, default=3000, help="ADMM iteration cap per setting of --admm-sweep")
+    ap.add_argument("--passes-only", choices=["headline", "precision", "precision_fp32"],
+                    help="only the in-solve per-pass timing on that grid (warmup W, then K timed ADMM "
+                         "iterations); prints one JSON line (for kernel traces and counters)")
     return ap.parse_args()
 
 
@@ -144,6 +153,43 @@ def measured_traffic(pass_name, tile_width):
     return rec.get("traffic_bytes")
 
 
+def in_solve_passes(ctx, yhat, state, torch):
+    """Per-pass figures of the PCG iteration measured inside ADMM iterations
+    that continue from `state` (the context's admm_maxit of them): mean kernel
+    duration per launch from events bound to each dispatch, algorithmic bytes
+    per launch, GB/s, and the pass's share of the PCG passes' GPU time."""
+    ctx.pass_timing(True)
+    ctx.admm_solve(yhat, state=state)
+    torch.cuda.synchronize()
+    stats = ctx.pass_stats()
+    ctx.pass_timing(False)
+    total = sum(us * n for us, n, _ in stats.values())
+    out = {}
+    for name, (us, n, by) in stats.items():
+        out[name] = {"us": round(us, 2), "launches": n, "bytes": by, "GB/s": round(by / us / 1e3, 1),
+                     "share": round(us * n / total, 4)}
+    return out
+
+
+def passes_only_leg(fde, torch, grid, warmup, steps):
+    """The in-solve per-pass table alone: `warmup` ADMM iterations from zero,
+    then `steps` more with pass timing, on the headline grid or the 1024^2 x 32
+    precision form (FP64, or with the FP32 preconditioner)."""
+    import workloads as W
+
+    w = W.headline() if grid == "headline" else W.precision()
+    fp32 = 1 if grid == "precision_fp32" else 0
+    yhat = torch.from_numpy(w.yhat).to("cuda")
+    prob, prm = fde.from_workload(w, precond_fp32=fp32, admm_tol=0.0, admm_maxit=max(warmup, 1))
+    with fde.Context(prob, prm) as ctx:
+        tiles = ctx.autotune()
+        state, _, _ = ctx.admm_solve(yhat)
+        ctx.set_params(fde.from_workload(w, precond_fp32=fp32, admm_tol=0.0, admm_maxit=steps)[1])
+        passes = in_solve_passes(ctx, yhat, state, torch)
+    return {"grid": grid, "shape": [w.nx, w.ny, w.nt], "autotune": tiles, "warmup": warmup, "steps": steps,
+            "passes": passes, "copy_kernel": copy_calibration(torch)}
+
+
 def paper_table5_leg(fde, torch):
     """The paper's test problem and protocol (Sec. 6.1; Caputo order 0.7,
     Riesz orders 1.3, box on both variables, dynamic Krylov tolerance, PCG from
@@ -190,6 +236,86 @@ def paper_table5_leg(fde, torch):
     return {"rows": rows, "paper_times": rec["time_note"]}
 
 
+SWEEP_DELTAS = (0.01, 0.03, 0.1, 0.4, 2.0, 10.0, 100.0)
+
+
+def admm_sweep_leg(fde, torch, w, yhat, cap):
+    """ADMM settings on the headline grid (Alg. 1, Sec. 6.1): the psi scaling
+    of the u copies (1: e_u = psi as in Sec. 6.1; 2: the constraint scaled,
+    the copies not), delta from the paper's pool of Sec. 6 and below it, and
+    rho in {1, 1.618}.  Each setting runs from zero to the stopping test at
+    1e-4, then resumes from that state to 1e-6 (resuming is exact), with at
+    most `cap` iterations in all.  FP64."""
+    rows = []
+    for ps in (1, 2):
+        for rho in (1.0, 1.618):
+            for delta in SWEEP_DELTAS:
+                prob, prm = fde.from_workload(w.replace(psi_scaling=ps, delta=delta, rho=rho), admm_tol=1e-4,
+                                              admm_maxit=cap)
+                rec = {"psi_scaling": ps, "rho": rho, "delta": delta}
+                with fde.Context(prob, prm) as c:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    state, st, status = c.admm_solve(yhat)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter() - t0
+                    rec["it_1e-4"] = st["admm_iters"] if status == 0 else None
+                    rec["s_1e-4"] = round(t1, 3) if status == 0 else None
+                    it, pcg, t = st["admm_iters"], st["pcg_total"], t1
+                    res = [st["r_p"], st["r_y"], st["r_u"]]
+                    if status == 0 and it < cap:
+                        c.set_params(fde.from_workload(w.replace(psi_scaling=ps, delta=delta, rho=rho),
+                                                       admm_tol=1e-6, admm_maxit=cap - it)[1])
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        state, st2, status2 = c.admm_solve(yhat, state=state)
+                        torch.cuda.synchronize()
+                        t += time.perf_counter() - t0
+                        it += st2["admm_iters"]
+                        pcg += st2["pcg_total"]
+                        res = [st2["r_p"], st2["r_y"], st2["r_u"]]
+                        rec["it_1e-6"] = it if status2 == 0 else None
+                        rec["s_1e-6"] = round(t, 3) if status2 == 0 else None
+                    else:
+                        rec["it_1e-6"] = rec["s_1e-6"] = None
+                rec.update({"iters": it, "pcg_total": pcg, "s": round(t, 3),
+                            "residuals": [float("%.3e" % r) for r in res]})
+                progress(f"sweep {rec}")
+                rows.append(rec)
+    return {"grid": [w.nx, w.ny, w.nt], "cap": cap, "rows": rows}
+
+
+def differentiation_leg(fde, torch, iters):
+    """The 512^2 x 32 differentiation form (orders 1.4/1.6, sinusoid-sum
+    target, gamma 1e-4, |u| <= 1): `iters` ADMM iterations from zero (the
+    forward pass), then the backward pass: gradients of the optimal value with
+    the adjoint solve D^T lambda = -J1 (y - yhat) - w_y (backward time stepping,
+    BiCGSTAB per step) and, for comparison, with lambda = psi p from the ADMM
+    multiplier (envelope form, no solve)."""
+    import workloads as W
+
+    w = W.differentiation()
+    yhat = torch.from_numpy(w.yhat).to("cuda")
+    prob, prm = fde.from_workload(w, admm_tol=0.0, admm_maxit=iters)
+    rec = {"grid": [w.nx, w.ny, w.nt], "admm_iters": iters}
+    with fde.Context(prob, prm) as ctx:
+        ctx.autotune()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        state, st, _ = ctx.admm_solve(yhat)
+        torch.cuda.synchronize()
+        rec["forward_s"] = round(time.perf_counter() - t0, 3)
+        dy = torch.empty_like(yhat)
+        lam = torch.empty_like(yhat)
+        for tag, adj in (("backward_adjoint_solve", True), ("backward_envelope", False)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, da, db = ctx.grad(yhat, state["y"], state["p"], state["wy"], adjoint_solve=adj, dyhat=dy, lam=lam)
+            torch.cuda.synchronize()
+            rec[tag] = {"s": round(time.perf_counter() - t0, 4), "dJ_dalpha": da, "dJ_dbeta": db}
+    return rec
+
+
 def batched_leg(fde, torch, cap):
     """64 uneven instances (sizes 64..512, nt 16/32, random orders and gamma, GRF
     targets), each run for `cap` ADMM iterations: concurrently with the FP32
@@ -200,7 +326,8 @@ def batched_leg(fde, torch, cap):
     ws = W.batched()
     yh = [torch.from_numpy(w.yhat).to("cuda") for w in ws]
     rec = {"instances": len(ws), "points": sum(w.N for w in ws), "admm_iters_per_instance": cap}
-    for tag, fp32, conc in (("concurrent_fp32_precond", 1, True), ("sequential_fp64", 0, False)):
+    for tag, fp32, conc in (("concurrent_fp32_precond", 1, True), ("concurrent_fp64", 0, True),
+                            ("sequential_fp64", 0, False)):
         probs, prms = zip(*[fde.from_workload(w, precond_fp32=fp32, admm_maxit=cap) for w in ws])
         with fde.Batch(list(probs), list(prms)) as b:
             torch.cuda.synchronize()
@@ -210,6 +337,8 @@ def batched_leg(fde, torch, cap):
         pcg = sum(s["pcg_total"] for s in stats)
         rec[tag] = {"s": round(dt, 3), "solves_per_s": round(len(ws) / dt, 2), "pcg_iters_per_s": round(pcg / dt, 1),
                     "pcg_total": pcg}
+    # concurrency alone (FP64 both ways), and concurrency with the FP32 preconditioner
+    rec["speedup_concurrency_fp64"] = round(rec["sequential_fp64"]["s"] / rec["concurrent_fp64"]["s"], 3)
     rec["speedup"] = round(rec["sequential_fp64"]["s"] / rec["concurrent_fp32_precond"]["s"], 3)
     return rec
 
@@ -228,6 +357,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     w = W.headline()
     yhat = torch.from_numpy(w.yhat).to("cuda")
+    if a.admm_sweep:
+        print(json.dumps({"admm_sweep": admm_sweep_leg(fde, torch, w, yhat, a.sweep_cap)}), flush=True)
+        return
+    if a.passes_only:
+        print(json.dumps(passes_only_leg(fde, torch, a.passes_only, a.warmup, a.steps)), flush=True)
+        return
     out = {"metric": "PCG iters/s + ADMM solve time, 256^2x64 grid; HBM GB/s; FP32-precond vs FP64",
            "unit": "PCG iters/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -247,31 +382,30 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     out["value"] = st["pcg_total"] / dt
+    out["value_window"] = f"ADMM iterations {a.warmup + 1}..{a.warmup + a.steps} of a cold start"
     out["ms_per_step"] = 1e3 * dt / a.steps
     out["pcg_per_admm_iter"] = st["pcg_total"] / a.steps
+    out["phase_s_per_step"] = {"rhs": round(st["t_rhs"] / a.steps, 6), "krylov": round(st["t_krylov"] / a.steps, 6),
+                               "update": round(st["t_update"] / a.steps, 6)}
 
-    # ---- per-pass kernel timing (HIP events on the library stream) ---------
-    passes = {}
-    for i, name in enumerate(fde.PASS_NAMES):
-        us, by = ctx.time_pass(i, reps=a.pass_reps)
-        passes[name] = {"us": round(us, 2), "GB/s": round(by / us / 1e3, 1), "bytes": by}
-    dom = max(passes, key=lambda k: passes[k]["us"])
-    achieved = passes[dom]["bytes"] / passes[dom]["us"] / 1e3
+    # ---- per-pass kernel durations inside the solve ------------------------
+    # The same K ADMM iterations again from the reached state, the PCG passes as
+    # plain launches with HIP events bound to each pass's own dispatch.
+    progress(f"pass timing over {a.steps} ADMM iterations")
+    passes = in_solve_passes(ctx, yhat, state, torch)
+    dom = max(passes, key=lambda k: passes[k]["share"])
     copy = copy_calibration(torch)
-    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    achieved = passes[dom]["GB/s"]
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": measured_traffic(dom, out["autotune"][0]),
-                       "bytes_per_launch": passes[dom]["bytes"], "copy_kernel": copy}
-    pcg_pass_us = sum(p["us"] for p in passes.values())
-    pcg_bytes = sum(p["bytes"] for p in passes.values())
+                       "bytes_per_launch": passes[dom]["bytes"], "us_per_launch": passes[dom]["us"],
+                       "launches": passes[dom]["launches"], "copy_kernel": copy}
     out["pcg_iteration_passes"] = passes
-    # The line passes are bound by FP64 arithmetic rather than HBM: nominal
-    # FFT flops (5 L log2 L per complex transform of length L = 2n) per launch
-    # against the FP64 vector peak.  Headline: x-lines carry d+(x) (three
-    # transforms per pair of lines); y-lines are constant-coefficient per
-    # column (two per pair).
-    import math
-
+    # The line passes are FP64-VALU-heavy FFTs: nominal FFT flops (5 L log2 L
+    # per complex transform of length L = 2n) per launch against the FP64
+    # vector peak.  Headline: x-lines carry d+(x) (three transforms per pair of
+    # lines); y-lines are constant-coefficient per column (two per pair).
     def fft_flops(n_lines, L, per_pair):
         return (n_lines / 2) * per_pair * 5.0 * L * math.log2(L)
 
@@ -282,6 +416,8 @@ def main():
         tf = fl / passes[name]["us"] / 1e6
         alu[name] = {"nominal_fft_flops": fl, "TFLOP/s": round(tf, 1), "frac_fp64_peak": round(tf / FP64_PEAK_TF, 3)}
     out["line_passes_alu"] = {"peak_TFLOP/s": FP64_PEAK_TF, "passes": alu}
+    pcg_pass_us = sum(p["us"] for p in passes.values())
+    pcg_bytes = sum(p["bytes"] for p in passes.values())
     out["pcg_iteration_model"] = {"us": round(pcg_pass_us, 1), "GB": round(pcg_bytes / 1e9, 4),
                                   "GB/s": round(pcg_bytes / pcg_pass_us / 1e3, 1)}
     ctx.close()
@@ -304,12 +440,14 @@ def main():
                        "pcg_total": st2["pcg_total"], "pcg_iters_per_s": round(st2["pcg_total"] / t, 1),
                        "ms_per_admm_iter": round(1e3 * t / st2["admm_iters"], 3), "converged": status == 0,
                        "residuals": [st2["r_p"], st2["r_y"], st2["r_u"]], "dual_inf": st2["dual_inf"],
-                       "J": st2["J"]}
+                       "J": st2["J"], "phase_s": {"rhs": round(st2["t_rhs"], 4), "krylov": round(st2["t_krylov"], 4),
+                                                  "update": round(st2["t_update"], 4)}}
                 if fp32:
                     rec["rel_diff_y_vs_fp64"] = float(torch.linalg.norm(s2["y"] - y64) / torch.linalg.norm(y64))
                     rec["rel_diff_u_vs_fp64"] = float(torch.linalg.norm(s2["u"] - u64) / torch.linalg.norm(u64))
                 out[tag] = rec
         out["admm_solve_s"] = out["fp64"]["admm_solve_s"]
+        out["pcg_iters_per_s_whole_solve"] = out["fp64"]["pcg_iters_per_s"]
 
         # Krylov counts on the variable-coefficient headline grid: S~ (eq. (3.10))
         # against the matching S^ (eq. (3.11)), under Algorithms 1 and 2, and the
@@ -351,6 +489,9 @@ def main():
                 sol[tag] = (s4["y"].clone(), s4["u"].clone())
             rec[tag] = {"s": round(t, 3), "pcg_total": st4["pcg_total"],
                         "pcg_iters_per_s": round(st4["pcg_total"] / t, 1)}
+        for tag in ("precision", "precision_fp32"):
+            progress(f"pass timing, {tag}")
+            rec["passes_" + tag] = passes_only_leg(fde, torch, tag, 2, 3)["passes"]
         (y64, u64), (y32, u32) = sol["fp64"], sol["fp32_precond"]
         rec["rel_diff_y"] = float(torch.linalg.norm(y32 - y64) / torch.linalg.norm(y64))
         rec["rel_diff_u"] = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
@@ -361,6 +502,11 @@ def main():
     if not a.no_paper:
         progress("paper test problem, Table 5 sizes")
         out["paper_table5"] = paper_table5_leg(fde, torch)
+
+    # ---- differentiation form: forward ADMM and the backward pass --------------
+    if not a.no_full:
+        progress("differentiation form 512^2 x 32: forward and backward")
+        out["differentiation"] = differentiation_leg(fde, torch, a.diff_iters)
 
     # ---- batched form: 64 uneven instances, concurrent vs sequential ---------
     if not a.no_batch:

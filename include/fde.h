@@ -140,6 +140,14 @@ typedef struct {
                              max(||J1 (y - yhat) + D^T lambda + mu_y||_inf,
                                  ||gamma J1 u + ctrl_sign lambda + mu_u||_inf)
                              with lambda = psi p, mu_y = w_y, mu_u = e_u w_u     */
+  /* GPU time per phase of Algorithm 1, seconds summed over the iterations
+   * (HIP events on the context stream at the phase boundaries; host waits
+   * between the Krylov chunks count in t_krylov):                           */
+  double t_rhs;           /* right-hand side of the x-step (step 1, with the
+                             B^T apply of eq. (3.9)'s right-hand side)         */
+  double t_krylov;        /* the x-step's Krylov solve (step 2)                  */
+  double t_update;        /* B y, recovery of p and u, box projection, dual
+                             updates and residual maxima (steps 3-6)            */
 } fde_admm_stats;
 
 /* Check a problem/parameter pair without touching the GPU.  FDE_OK or
@@ -299,6 +307,23 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
  *   8 x-inverse writing the direction p = z + beta p
  * Synchronises the stream. */
 fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* bytes);
+
+/* In-solve timing of the nine passes of the PCG iteration (the O(N log N)
+ * applies of Table 1 and the preconditioner of eq. (3.10)), for the roofline
+ * figure: with enable = 1, until disabled, every PCG iteration of fde_krylov
+ * and fde_admm_solve on this context runs as plain launches (no graph) with a
+ * pair of HIP events bound to each pass's own dispatch (hipExtLaunchKernel),
+ * and the kernel durations accumulate per pass (cleared by enable = 1).
+ * Results and iteration counts are those of the graph launches.  Implicit
+ * Euler only (FDE_EINVAL for another time order).  Synchronises the stream. */
+fde_status fde_pass_timing(fde_ctx* ctx, int enable);
+
+/* Accumulated in-solve pass figures, pass order as in fde_time_pass (host
+ * arrays of 9, each may be NULL): us = mean kernel duration per launch
+ * (microseconds), launches = dispatches timed (iterations enqueued after the
+ * solve's convergence return at once and are included, as in a kernel trace),
+ * bytes = algorithmic bytes of one launch (as fde_time_pass). */
+fde_status fde_pass_stats(fde_ctx* ctx, double* us, int32_t* launches, double* bytes);
 
 /* Autotuner of the FFT column tiles: times the widest, half and quarter
  * column-tile variants of the y-direction Toeplitz passes, the y-direction

@@ -28,6 +28,10 @@
 
 using fde::host::cd;
 
+namespace fde {
+thread_local PassEventQueue t_pass_events;
+}
+
 namespace {
 thread_local std::string g_err;
 
@@ -129,6 +133,9 @@ struct fde_ctx {
   double* h_scal = nullptr;  // pinned
   int* h_ints = nullptr;
   hipEvent_t ev = nullptr;   // marks completion of the last posted readback
+  // phase boundaries of an ADMM iteration (timing events): RHS start, Krylov
+  // start, Krylov end, update end
+  hipEvent_t ph_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<void*> allocs;
 
   // one PCG iteration captured as a HIP graph (re-captured when the
@@ -139,6 +146,13 @@ struct fde_ctx {
   hipGraphExec_t pcg_exec[2] = {nullptr, nullptr};
   const double* pcg_graph_x = nullptr;
   bool use_graph = true;
+  // in-solve pass timing (fde_pass_timing): plain PCG launches with a pair of
+  // events bound to each of the nine passes, harvested after every readback
+  bool ptime = false;
+  std::vector<hipEvent_t> pt_ev;  // pool of event pairs
+  int pt_used = 0;                // pairs enqueued since the last harvest
+  double pt_us[fde::kNumPasses] = {};
+  int64_t pt_n[fde::kNumPasses] = {};
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
   int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
   int conv_sep = -1;  // PCG convergence test: -1 by grid size, 0 fused in the y-forward pass, 1 on its own
@@ -381,7 +395,45 @@ fde_status sync_scalars(fde_ctx* c) {
 // convergence test inside the following pass ; z = S~^{-1} r with (r, z)
 // partials ; beta inside p = z + beta p.
 // Every kernel returns at once when the device flag says the solve is done.
+hipError_t enqueue_pcg_iteration_passes(fde_ctx* c, double* x);
+
+// With pass timing on, the nine pass launches of the iteration take the next
+// nine event pairs of the context's pool (grown on demand).
 hipError_t enqueue_pcg_iteration(fde_ctx* c, double* x) {
+  using namespace fde;
+  if (!c->ptime) return enqueue_pcg_iteration_passes(c, x);
+  const size_t need = 2 * (size_t)(c->pt_used + kNumPasses);
+  while (c->pt_ev.size() < need) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    c->pt_ev.push_back(ev);
+  }
+  t_pass_events = PassEventQueue{c->pt_ev.data() + 2 * (size_t)c->pt_used, kNumPasses, 0};
+  const hipError_t e = enqueue_pcg_iteration_passes(c, x);
+  const int taken = t_pass_events.next;
+  t_pass_events = PassEventQueue{};
+  if (e != hipSuccess) return e;
+  if (taken != kNumPasses) return hipErrorUnknown;  // the pass list changed
+  c->pt_used += kNumPasses;
+  return hipSuccess;
+}
+
+// Kernel durations of the pass launches enqueued since the last harvest (all
+// complete: called after a readback of the stream)
+hipError_t harvest_pass_times(fde_ctx* c) {
+  for (int k = 0; k < c->pt_used; ++k) {
+    float ms = 0;
+    const hipError_t e = hipEventElapsedTime(&ms, c->pt_ev[2 * (size_t)k], c->pt_ev[2 * (size_t)k + 1]);
+    if (e != hipSuccess) return e;
+    c->pt_us[k % fde::kNumPasses] += 1000.0 * ms;
+    c->pt_n[k % fde::kNumPasses] += 1;
+  }
+  c->pt_used = 0;
+  return hipSuccess;
+}
+
+hipError_t enqueue_pcg_iteration_passes(fde_ctx* c, double* x) {
   using namespace fde;
   const int* done = c->ints + kDone;
   int nbS = 0, nb1 = 0, nb5 = 0;
@@ -477,7 +529,7 @@ fde_status ensure_pcg_graph(fde_ctx* c, double* x) {
 // enqueue n PCG iterations (graph launches of kGraphIters and of one)
 hipError_t launch_pcg_iterations(fde_ctx* c, double* x, int n) {
   hipError_t e = hipSuccess;
-  if (!c->use_graph) {
+  if (!c->use_graph || c->ptime) {
     for (int k = 0; k < n && e == hipSuccess; ++k) e = enqueue_pcg_iteration(c, x);
     return e;
   }
@@ -536,7 +588,7 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
   a.scal_w = c->scal;
   a.ints = c->ints;
   HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
-  if (c->use_graph) {
+  if (c->use_graph && !c->ptime) {
     const fde_status st = ensure_pcg_graph(c, x);
     if (st != FDE_OK) return st;
   }
@@ -549,6 +601,13 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
 // returns 1 when finished (kr->status, iters, relres set), 0 when more work was enqueued
 int krylov_continue(fde_ctx* c, KrylovRun* kr) {
   using namespace fde;
+  if (c->ptime) {
+    const hipError_t he = harvest_pass_times(c);
+    if (he != hipSuccess) {
+      kr->status = (fde_status)fail(FDE_EHIP, std::string("pass timing: ") + hipGetErrorString(he));
+      return 1;
+    }
+  }
   if (!(c->h_ints[kDone] || kr->enqueued >= kr->maxit)) {
     const int more = std::min(2, kr->maxit - kr->enqueued);
     const hipError_t e = launch_pcg_iterations(c, kr->x, more);
@@ -789,6 +848,7 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   const auto& s = c->su;
   const fde_admm_params& q = c->prm;
   const double psi = s.psi;
+  HIP_TRY(hipEventRecord(c->ph_ev[0], c->stream));
   // 1. b = B^T((1-rho) p - M_p^{-1} r) + rho(J1 yhat - e_y wy + e_y^2 zy/delta)
   if (!R->have_rhs) HIP_TRY(fde::launch_admm_rhs(R->k, R->f, psi, c->stream));
   R->have_rhs = false;
@@ -804,6 +864,7 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
     const double tol = q.tol_mode == 1 ? 0.05 * std::fmax(R->prev_min, 1e-4) : q.krylov_tol;
     R->tp = now();
     R->phase = PH_PCG;
+    HIP_TRY(hipEventRecord(c->ph_ev[1], c->stream));
     return minres_begin(c, fde::Triple{c->bvec, R->f.Ru, c->mr_rhs}, fde::Triple{R->f.y, R->f.u, R->f.p}, tol,
                         q.krylov_maxit, q.pcg_cold_start != 0, R->predict, &R->mr);
   }
@@ -817,6 +878,7 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   R->have_byp = false;
   R->tp = now();
   R->phase = PH_PCG;
+  HIP_TRY(hipEventRecord(c->ph_ev[1], c->stream));
   return krylov_begin(c, c->bvec, R->f.y, tol, q.krylov_maxit, R->predict, &R->kr, sx);
 }
 
@@ -894,6 +956,7 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
       R->st.pcg_last = it;
       if (it > R->st.pcg_max) R->st.pcg_max = it;
       // 3-5. By ; p, u recovery ; projection ; dual updates ; residual maxima
+      HIP_TRY(hipEventRecord(c->ph_ev[2], c->stream));
       HIP_TRY(apply_op(c, R->f.y, c->By, false, psi, c->fa, c->fb, nullptr, nullptr, nullptr, nullptr, nullptr,
                        nullptr, nullptr));
       int nb = 0;
@@ -905,11 +968,20 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
       R->have_byp = !mr;
       R->have_rhs = true;
       HIP_TRY(fde::launch_max3_finalize(c->part_max, nb, c->scal, c->stream));
+      HIP_TRY(hipEventRecord(c->ph_ev[3], c->stream));
       R->phase = PH_RES;
       return post_readback(c);
     }
     case PH_RES: {
       fde_admm_stats& st = R->st;
+      {
+        // this iteration's phases (complete: the readback behind them has finished)
+        float ms[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) HIP_TRY(hipEventElapsedTime(&ms[k], c->ph_ev[k], c->ph_ev[k + 1]));
+        st.t_rhs += 1e-3 * ms[0];
+        st.t_krylov += 1e-3 * ms[1];
+        st.t_update += 1e-3 * ms[2];
+      }
       st.admm_iters = R->j;
       st.r_p = c->h_scal[fde::kResP];
       st.r_y = c->h_scal[fde::kResY];
@@ -952,12 +1024,18 @@ fde_status admm_advance(fde_ctx* c, AdmmRun* R) {
 
 fde_status free_all(fde_ctx* c) {
   drop_pcg_graph(c);
+  for (hipEvent_t ev : c->pt_ev) (void)hipEventDestroy(ev);
+  c->pt_ev.clear();
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->cap_stream = nullptr;
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->ev) (void)hipEventDestroy(c->ev);
   c->ev = nullptr;
+  for (hipEvent_t& pe : c->ph_ev) {
+    if (pe) (void)hipEventDestroy(pe);
+    pe = nullptr;
+  }
   if (c->h_ms) (void)hipHostFree(c->h_ms);
   c->h_ms = nullptr;
   c->mr_ready = false;
@@ -1268,6 +1346,8 @@ fde_status create_impl(const fde_problem* prob, const fde_admm_params* prm, void
   if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_scal, sizeof(double) * fde::kNumScalars, hipHostMallocDefault));
   if (e == hipSuccess) chk(hipHostMalloc((void**)&c->h_ints, sizeof(int) * fde::kNumInts, hipHostMallocDefault));
   if (e == hipSuccess) chk(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
+  for (hipEvent_t& pe : c->ph_ev)
+    if (e == hipSuccess) chk(hipEventCreate(&pe));
   if (e == hipSuccess) chk(hipMemset(c->scal, 0, sizeof(double) * fde::kNumScalars));
   if (e == hipSuccess) chk(hipMemset(c->ints, 0, sizeof(int) * fde::kNumInts));
   if (e != hipSuccess) {
@@ -1722,6 +1802,22 @@ hipError_t time_launches(fde_ctx* c, int reps, F&& launch, double* us) {
   *us = 1000.0 * ms / reps;
   return e;
 }
+// Algorithmic bytes of one launch of PCG pass `which` (every field it reads or
+// writes counted once; the half spectrum in the preconditioner's precision)
+double pass_bytes(fde_ctx* c, int which) {
+  const double f8 = 8.0 * (double)c->N;
+  const double sb = (double)c->H * c->ny * c->nt * (c->fp32 ? 8 : 16);
+  switch (which) {
+    case 0: case 2: return 2 * f8;     // read v, write out
+    case 1: return 3 * f8;             // read v, acc; write out
+    case 3: return 4 * f8;             // read v, acc, extra (= the dot operand); write out
+    case 4: return 6 * f8 + sb;        // read r, q, x, p; write r, x, spectrum
+    case 5: case 6: case 7: return 2 * sb;
+    case 8: return 2 * f8 + sb;        // read spectrum, p; write p
+    default: return 0;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1840,16 +1936,7 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
     HIP_TRY(hipMemcpy(c->scal, h.data(), sizeof(double) * kNumScalars, hipMemcpyHostToDevice));
   }
   const double psi = c->su.psi, sti = psi / c->su.ht;
-  const double f8 = 8.0 * (double)N;
-  double b = 0;
-  switch (which) {
-    case 0: case 2: b = 2 * f8; break;  // read v, write out
-    case 1: b = 3 * f8; break;          // read v, acc; write out
-    case 3: b = 4 * f8; break;          // read v, acc, extra (= the dot operand); write out
-    case 4: b = 6 * f8 + (double)sb; break;  // read r, q, x, p; write r, x, spectrum
-    case 5: case 6: case 7: b = 2.0 * (double)sb; break;
-    case 8: b = 2 * f8 + (double)sb; break;  // read spectrum, p; write p
-  }
+  const double b = pass_bytes(c, which);
   auto launch = [&](int rot) -> hipError_t {
     double* const* f = sets[rot & 1];
     switch (which) {
@@ -1899,6 +1986,32 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
   (void)hipEventDestroy(e1);
   if (us) *us = 1000.0 * ms / reps;
   if (bytes) *bytes = b;
+  return FDE_OK;
+}
+
+fde_status fde_pass_timing(fde_ctx* ctx, int enable) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  if (ctx->frac_t) return (fde_status)fail(FDE_EINVAL, "fde_pass_timing: the pass list is that of alpha_t = 1");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->ptime = enable != 0;
+  ctx->pt_used = 0;
+  if (ctx->ptime) {
+    for (int k = 0; k < fde::kNumPasses; ++k) {
+      ctx->pt_us[k] = 0;
+      ctx->pt_n[k] = 0;
+    }
+  }
+  return FDE_OK;
+}
+
+fde_status fde_pass_stats(fde_ctx* ctx, double* us, int32_t* launches, double* bytes) {
+  if (check_ctx(ctx) != FDE_OK) return FDE_EINVAL;
+  for (int k = 0; k < fde::kNumPasses; ++k) {
+    const int64_t n = ctx->pt_n[k];
+    if (us) us[k] = n > 0 ? ctx->pt_us[k] / (double)n : 0.0;
+    if (launches) launches[k] = (int32_t)n;
+    if (bytes) bytes[k] = pass_bytes(ctx, k);
+  }
   return FDE_OK;
 }
 

@@ -1,5 +1,6 @@
 // Internal declarations shared by the host code and the kernel translation units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,6 +23,31 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int per = nb / kXcd, rem = nb % kXcd;
   const int x = b % kXcd, k = b / kXcd;
   return x * per + (x < rem ? x : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// In-solve pass timing.  The host may queue pairs of HIP events for the next
+// pass launches of its thread; each launch of a line pass or a preconditioner
+// pass then takes the next pair, which hipExtLaunchKernel binds to that
+// dispatch (start and end of the kernel's own execution).  Without queued
+// events the launch is a plain one.
+// ---------------------------------------------------------------------------
+constexpr int kNumPasses = 9;  // passes of one PCG iteration (implicit Euler)
+struct PassEventQueue {
+  const hipEvent_t* ev = nullptr;  // n pairs (start, stop)
+  int n = 0, next = 0;
+};
+extern thread_local PassEventQueue t_pass_events;
+
+template <typename Arg>
+inline void launch_pass(void (*kern)(Arg), int blocks, int threads, hipStream_t s, const Arg& a) {
+  PassEventQueue& q = t_pass_events;
+  if (q.next < q.n) {
+    const int k = q.next++;
+    hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, q.ev[2 * k], q.ev[2 * k + 1], 0, a);
+  } else {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, a);
+  }
 }
 
 // 16-byte accesses of two adjacent doubles (fields are 16-byte aligned and nx is even)

@@ -415,12 +415,12 @@ static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) 
   const int blocks = (pairs + LPB - 1) / LPB;
   if (nb) *nb = blocks;
   if (fwd) {
-    if (a.q) k_pre_xfwd<L, TS, true><<<blocks, kPreThreads, 0, s>>>(a);
-    else k_pre_xfwd<L, TS, false><<<blocks, kPreThreads, 0, s>>>(a);
+    if (a.q) launch_pass(k_pre_xfwd<L, TS, true>, blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xfwd<L, TS, false>, blocks, kPreThreads, s, a);
   } else {
-    if (a.pdir == 1) k_pre_xinv<L, TS, 2><<<blocks, kPreThreads, 0, s>>>(a);
-    else if (a.partial2) k_pre_xinv<L, TS, 1><<<blocks, kPreThreads, 0, s>>>(a);
-    else k_pre_xinv<L, TS, 0><<<blocks, kPreThreads, 0, s>>>(a);
+    if (a.pdir == 1) launch_pass(k_pre_xinv<L, TS, 2>, blocks, kPreThreads, s, a);
+    else if (a.partial2) launch_pass(k_pre_xinv<L, TS, 1>, blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xinv<L, TS, 0>, blocks, kPreThreads, s, a);
   }
   return hipGetLastError();
 }
@@ -429,8 +429,8 @@ template <int L, typename TS, int S>
 static hipError_t pre_y_S(const PrecondArgs& a, int sign, hipStream_t s) {
   using C = CCfg<L, S>;
   const int blocks = ((a.H + C::P - 1) / C::P) * a.nt;
-  if (sign < 0) k_pre_cc<L, TS, 0, -1, S><<<blocks, C::NT, 0, s>>>(a);
-  else k_pre_cc<L, TS, 0, +1, S><<<blocks, C::NT, 0, s>>>(a);
+  if (sign < 0) launch_pass(k_pre_cc<L, TS, 0, -1, S>, blocks, C::NT, s, a);
+  else launch_pass(k_pre_cc<L, TS, 0, +1, S>, blocks, C::NT, s, a);
   return hipGetLastError();
 }
 
@@ -447,8 +447,8 @@ template <int L, typename TS, int S>
 static hipError_t pre_t_S(const PrecondArgs& a, hipStream_t s) {
   using C = CCfg<L, S>;
   const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
-  if (a.div_mode == 1) k_pre_cc<L, TS, 2, -1, S><<<blocks, C::NT, 0, s>>>(a);
-  else k_pre_cc<L, TS, 1, -1, S><<<blocks, C::NT, 0, s>>>(a);
+  if (a.div_mode == 1) launch_pass(k_pre_cc<L, TS, 2, -1, S>, blocks, C::NT, s, a);
+  else launch_pass(k_pre_cc<L, TS, 1, -1, S>, blocks, C::NT, s, a);
   return hipGetLastError();
 }
 

@@ -386,11 +386,11 @@ static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t 
   const int blocks = (pairs + LPB - 1) / LPB;
   if (nb) *nb = blocks;
   if (var) {
-    if (tr) k_xpass<L, true, true><<<blocks, kLineThreads, 0, s>>>(a);
-    else k_xpass<L, true, false><<<blocks, kLineThreads, 0, s>>>(a);
+    if (tr) launch_pass(k_xpass<L, true, true>, blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, true, false>, blocks, kLineThreads, s, a);
   } else {
-    if (tr) k_xpass<L, false, true><<<blocks, kLineThreads, 0, s>>>(a);
-    else k_xpass<L, false, false><<<blocks, kLineThreads, 0, s>>>(a);
+    if (tr) launch_pass(k_xpass<L, false, true>, blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, false, false>, blocks, kLineThreads, s, a);
   }
   return hipGetLastError();
 }
@@ -402,14 +402,14 @@ static hipError_t ypass_LS(const LinePassArgs& a, bool tr, bool var, hipStream_t
   const int blocks = tiles * a.nt;
   if (nb) *nb = blocks;
   if (a.col_coef) {
-    if (tr) k_ypass<L, false, true, S, true><<<blocks, C::NT, 0, s>>>(a);
-    else k_ypass<L, false, false, S, true><<<blocks, C::NT, 0, s>>>(a);
+    if (tr) launch_pass(k_ypass<L, false, true, S, true>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S, true>, blocks, C::NT, s, a);
   } else if (var) {
-    if (tr) k_ypass<L, true, true, S><<<blocks, C::NT, 0, s>>>(a);
-    else k_ypass<L, true, false, S><<<blocks, C::NT, 0, s>>>(a);
+    if (tr) launch_pass(k_ypass<L, true, true, S>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, true, false, S>, blocks, C::NT, s, a);
   } else {
-    if (tr) k_ypass<L, false, true, S><<<blocks, C::NT, 0, s>>>(a);
-    else k_ypass<L, false, false, S><<<blocks, C::NT, 0, s>>>(a);
+    if (tr) launch_pass(k_ypass<L, false, true, S>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S>, blocks, C::NT, s, a);
   }
   return hipGetLastError();
 }

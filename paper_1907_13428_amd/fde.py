@@ -24,6 +24,7 @@ _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -
 EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
             "fde_apply_A_noalloc",
             "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_set_bounds", "fde_admm_solve", "fde_grad", "fde_time_pass",
+            "fde_pass_timing", "fde_pass_stats",
             "fde_autotune", "fde_batch_create", "fde_batch_destroy", "fde_batch_solve", "fde_last_error",
             "fde_version"]
 
@@ -58,7 +59,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("admm_iters", ctypes.c_int32), ("pcg_total", ctypes.c_int32), ("pcg_last", ctypes.c_int32),
                 ("pcg_max", ctypes.c_int32), ("r_p", ctypes.c_double), ("r_y", ctypes.c_double),
                 ("r_u", ctypes.c_double), ("J", ctypes.c_double), ("t_total", ctypes.c_double),
-                ("t_pcg", ctypes.c_double), ("dual_inf", ctypes.c_double)]
+                ("t_pcg", ctypes.c_double), ("dual_inf", ctypes.c_double), ("t_rhs", ctypes.c_double),
+                ("t_krylov", ctypes.c_double), ("t_update", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,6 +94,8 @@ def lib():
         L.fde_grad.argtypes = [P, P, P, P, P, ctypes.c_int, P, D, P]
         L.fde_time_pass.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
         L.fde_autotune.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.fde_pass_timing.argtypes = [P, ctypes.c_int]
+        L.fde_pass_stats.argtypes = [P, D, ctypes.POINTER(ctypes.c_int32), D]
         PP = ctypes.POINTER(ctypes.c_void_p)
         L.fde_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Problem), ctypes.POINTER(Params),
                                        ctypes.POINTER(P)]
@@ -297,6 +301,18 @@ class Context:
         b = ctypes.c_double()
         _check(lib().fde_time_pass(self._h, int(which), int(reps), ctypes.byref(us), ctypes.byref(b)), False)
         return us.value, b.value
+
+    def pass_timing(self, enable=True):
+        """Time the nine PCG passes inside the following solves (plain launches, events per pass)."""
+        _check(lib().fde_pass_timing(self._h, int(bool(enable))), False)
+
+    def pass_stats(self):
+        """{pass name: (mean us per launch, launches, algorithmic bytes per launch)} of the timed solves."""
+        us = (ctypes.c_double * 9)()
+        n = (ctypes.c_int32 * 9)()
+        b = (ctypes.c_double * 9)()
+        _check(lib().fde_pass_stats(self._h, us, n, b), False)
+        return {name: (us[i], n[i], b[i]) for i, name in enumerate(PASS_NAMES)}
 
     def grad(self, yhat, y, p, wy=None, adjoint_solve=False, dyhat=None, lam=None):
         """(dJ/dyhat field, dJ/dalpha, dJ/dbeta) at an ADMM solution."""

@@ -56,9 +56,11 @@ def test_headline_S_and_preconditioner_full(headline):
     v = W.random_field(w.shape, 22)
     y = zeros(w.shape)
     ctx.apply_S(dev(v), y)
-    assert rel(host(y), admm.apply_S(d, sc, v)) <= 1e-12
+    got, ref = host(y), admm.apply_S(d, sc, v)
+    assert rel(got, ref) <= 1e-12 and max_rel(got, ref) <= 1e-11, (rel(got, ref), max_rel(got, ref))
     ctx.precond(dev(v), y)
-    assert rel(host(y), precond.apply_precond(precond.precond_tables(w, d), v)) <= 1e-12
+    got, ref = host(y), precond.apply_precond(precond.precond_tables(w, d), v)
+    assert rel(got, ref) <= 1e-12 and max_rel(got, ref) <= 1e-11, (rel(got, ref), max_rel(got, ref))
 
 
 def test_headline_pcg_iterations_full(headline):
@@ -80,6 +82,7 @@ def test_headline_pcg_iterations_full(headline):
                                    np.zeros(w.shape), 1e-30, 5)
     assert itr == 5 and not conv
     assert rel(host(x), xr) <= 1e-10, rel(host(x), xr)
+    assert max_rel(host(x), xr) <= 1e-10, max_rel(host(x), xr)
     assert abs(relres - relr) <= 1e-8 * relr
 
 
@@ -115,8 +118,8 @@ def test_headline_admm_full(headline):
         assert st1["admm_iters"] == 1
         assert abs(st1["pcg_total"] - ref.pcg_iters[0]) <= 1
         for k in ("y", "u", "zy", "zu", "p", "wy", "wu"):
-            r = rel(host(state[k]), getattr(ref, k))
-            assert r <= 1e-7, (k, r)
+            got, want = host(state[k]), getattr(ref, k)
+            assert rel(got, want) <= 1e-7 and max_rel(got, want) <= 1e-7, (k, rel(got, want), max_rel(got, want))
     finally:
         ctx.set_params(fde.from_workload(w)[1])
 
@@ -219,6 +222,30 @@ def test_batch_real_sizes_concurrent_equals_sequential():
     pts = sample_points(big, 24, 27)
     ref = op.sampled_D(op.disc_from(big), v, pts)
     assert max(abs(got[p] - r) for p, r in zip(pts, ref)) <= 1e-11 * float(np.max(np.abs(ref)))
+
+
+def test_batch_real_size_instance_against_oracle():
+    """One real-size instance of the uneven batch (a 192 x 384 x 16 grid), run
+    inside a batch of two for 2 ADMM iterations: every iterate field against
+    the oracle's 2 iterations, element by element (max-relative and 2-norm)."""
+    banner("full size: batch instance 192x384x16 vs oracle")
+    ws = W.batched()
+    inst = next((x for x in ws if (x.nx, x.ny, x.nt) == (192, 384, 16)), None)
+    if inst is None:  # the seeded draw has no such grid: take the same recipe at that size
+        inst = ws[0].replace(nx=192, ny=384, nt=16)
+        inst.yhat = W.target_grf(192, 384, 16, W.BASE_SEED + 4)
+    small = ws[0]
+    pair = [inst, small]
+    probs, prms = zip(*[fde.from_workload(x, admm_tol=0.0, admm_maxit=2) for x in pair])
+    with fde.Batch(list(probs), list(prms)) as b:
+        states, stats, status = b.solve([dev(x.yhat) for x in pair], concurrent=True)
+        got = {k: host(v) for k, v in states[0].items()}
+    assert stats[0]["admm_iters"] == 2
+    ref = admm.admm_solve(inst, iters=2)
+    assert abs(stats[0]["pcg_total"] - sum(ref.pcg_iters)) <= 2
+    for k in ("y", "u", "zy", "zu", "p", "wy", "wu"):
+        want = getattr(ref, k)
+        assert rel(got[k], want) <= 1e-7 and max_rel(got[k], want) <= 1e-7, (k, rel(got[k], want))
 
 
 def test_precision_form_subsample_fp32_against_fp64_oracle():
