@@ -316,6 +316,42 @@ def differentiation_leg(fde, torch, iters):
     return rec
 
 
+def paper_tables_leg(fde, torch):
+    """Tables 2, 3, 4, 6 and 7 of the paper (Sec. 6.2; all on the 50^3 grid):
+    the rows of tests/golden/paper_tables.json under the Sec. 6.1 protocol, FP64
+    on the GPU, beside the printed figures (MATLAB on a CPU)."""
+    import workloads as W
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")) as f:
+        rec = json.load(f)
+    bound = lambda v: -math.inf if v == "-inf" else float(v)
+    rows = []
+    for row in (dict(zip(rec["columns"], r)) for r in rec["rows"]):
+        n = row["n"]
+        w = W.paper_test(n, alpha_t=row["alpha"], beta=row["beta"], gamma=row["gamma"], ya=bound(row["ya"]),
+                         ua=bound(row["ua"]), delta=row["delta"])
+        prob, prm = fde.from_workload(w)
+        yhat = torch.from_numpy(w.yhat).to("cuda")
+        with fde.Context(prob, prm) as ctx:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            state, st, status = ctx.admm_solve(yhat)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            h = 1.0 / (n + 1)
+            e2 = ((state["y"] - yhat) ** 2).sum(dim=(1, 2))
+            e2[-1] *= 0.5
+            el2 = float(torch.sqrt(h * h * (w.T / w.nt) * e2.sum()))
+        rows.append({"table": row["table"], "alpha": row["alpha"], "beta": row["beta"], "gamma": row["gamma"],
+                     "ya": row["ya"], "ua": row["ua"], "delta": row["delta"], "converged": status == 0,
+                     "admm_iters": st["admm_iters"], "paper_admm_iters": row["admm_iters"],
+                     "pcg_avg": round(st["pcg_total"] / max(st["admm_iters"], 1), 2),
+                     "paper_pcg_avg": row["pcg_avg"], "E_L2": round(el2, 4), "paper_E_L2": row["E_L2"],
+                     "dual_inf": st["dual_inf"], "paper_dual_inf": row["dual_inf"], "s": round(dt, 4),
+                     "paper_s": row["time_s"]})
+    return {"rows": rows, "paper_times": rec["time_note"]}
+
+
 def batched_leg(fde, torch, cap):
     """64 uneven instances (sizes 64..512, nt 16/32, random orders and gamma, GRF
     targets), each run for `cap` ADMM iterations: concurrently with the FP32
@@ -502,6 +538,8 @@ def main():
     if not a.no_paper:
         progress("paper test problem, Table 5 sizes")
         out["paper_table5"] = paper_table5_leg(fde, torch)
+        progress("paper test problem, Tables 2, 3, 4, 6, 7")
+        out["paper_tables"] = paper_tables_leg(fde, torch)
 
     # ---- differentiation form: forward ADMM and the backward pass --------------
     if not a.no_full:

@@ -60,7 +60,10 @@ typedef enum {
 /* Problem description (Sec. 4, eqs. (4.2)-(4.10)). */
 typedef struct {
   int32_t nx, ny, nt;     /* interior nodes per axis; each 2^a 3^b with b <= 1,
-                             4 <= n <= 1024                                     */
+                             4 <= n <= 1024, or one of 50, 80, 100, 160 (the
+                             paper's grids of Sec. 6.2; radix-5 transforms in
+                             the preconditioner, a longer circulant embedding
+                             in the operator)                                   */
   double T;               /* final time (> 0); ht = T / nt                      */
   double alpha, beta;     /* fractional orders along x and y, each in (1, 2]    */
   const double* dplus;    /* (host) ny*nx coefficient field d+, row j = y_j;

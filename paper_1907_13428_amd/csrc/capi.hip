@@ -239,6 +239,7 @@ hipError_t xpass(fde_ctx* c, const double* in, double* out, bool tr, double s_ti
   fde::LinePassArgs a = line_args(c);
   a.in = in;
   a.out = out;
+  a.L = c->su.x.L;
   a.tw = c->twx_emb;
   if (c->var) {
     a.lamA = tr ? c->lxTA : c->lxA;
@@ -259,6 +260,7 @@ hipError_t ypass(fde_ctx* c, const double* in, const double* acc, double* out, b
   fde::LinePassArgs a = line_args(c);
   a.in = in;
   a.out = out;
+  a.L = c->su.y.L;
   a.tw = c->twy_emb;
   a.lamA = tr ? c->lyTA : c->lyA;
   a.lamB = tr ? c->lyTB : c->lyB;
@@ -284,6 +286,7 @@ hipError_t tpass(fde_ctx* c, const double* in, const double* acc, double* out, b
   a.nx = c->nx * c->ny;
   a.ny = c->nt;
   a.nt = 1;
+  a.L = c->su.Lt;
   a.in = in;
   a.out = out;
   a.acc = acc;
@@ -1078,6 +1081,7 @@ struct SliceOps {
     a.nt = 1;
     a.in = x;
     a.out = c->fa;
+    a.L = c->su.x.L;
     a.tw = c->twx_emb;
     a.lamA = c->lxTA;
     a.lamB = c->lxTB;
@@ -1090,6 +1094,7 @@ struct SliceOps {
     b.in = x;
     b.acc = c->fa;
     b.out = y;
+    b.L = c->su.y.L;
     b.tw = c->twy_emb;
     b.lamA = c->lyTA;
     b.lamB = c->lyTB;
@@ -1721,6 +1726,7 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   fde::LinePassArgs a = line_args(c);
   a.in = y;
   a.out = c->fa;
+  a.L = c->su.x.L;
   a.tw = c->twx_emb;
   a.lamA = c->dxA;
   a.lamB = c->dxB;
@@ -1730,6 +1736,7 @@ fde_status fde_grad(fde_ctx* ctx, const double* yhat, const double* y, const dou
   fde::LinePassArgs b = line_args(c);
   b.in = y;
   b.out = c->fb;
+  b.L = c->su.y.L;
   b.tw = c->twy_emb;
   b.lamA = c->dyA;
   b.lamB = c->dyB;
@@ -1879,7 +1886,7 @@ fde_status fde_autotune(fde_ctx* ctx, int32_t* choices) {
   c->tile_pre_t = best[2];
   drop_pcg_graph(c);  // the captured iteration used the previous tiles
   if (choices) {
-    choices[0] = ypass_tile_width(2 * c->ny, best[0]);
+    choices[0] = ypass_tile_width(c->su.y.L, best[0]);
     choices[1] = best[1];
     choices[2] = best[2];
   }
@@ -1913,7 +1920,7 @@ fde_status fde_time_pass(fde_ctx* ctx, int which, int reps, double* us, double* 
   // the (r, r) partials (zero, against a negative tolerance: never met).
   int nbS = 0, nb1 = 0;
   if (which == 4) {
-    const int P = ypass_tile_width(2 * c->ny, c->tile_line_y);
+    const int P = ypass_tile_width(c->su.y.L, c->tile_line_y);
     nbS = ((c->nx + 2 * P - 1) / (2 * P)) * c->nt;
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(c->part_pq), 0x3FF00000, 2 * (size_t)nbS,
                               c->stream));

@@ -79,6 +79,32 @@ template <int SIGN, typename V> struct Dft<4, SIGN, V> {
   }
 };
 
+// 5-point DFT: with t1 = a1 + a4, t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3 and
+// c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5):
+//   X0 = a0 + t1 + t2
+//   X1, X4 = a0 + c1 t1 + c2 t2 +- SIGN i (s1 t3 + s2 t4)
+//   X2, X3 = a0 + c2 t1 + c1 t2 +- SIGN i (s2 t3 - s1 t4)
+template <int SIGN, typename V> struct Dft<5, SIGN, V> {
+  __device__ __forceinline__ static void run(V* a) {
+    using R = decltype(a[0].x);
+    const R c1 = R(0.3090169943749474241022934171828190588602);   // cos(2 pi / 5)
+    const R c2 = R(-0.8090169943749474241022934171828190588602);  // cos(4 pi / 5)
+    const R s1 = R(0.9510565162951535721164393333793821434057);   // sin(2 pi / 5)
+    const R s2 = R(0.5877852522924731291687059546390727685977);   // sin(4 pi / 5)
+    const V t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const V t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+    const V m1 = V{a[0].x + c1 * t1.x + c2 * t2.x, a[0].y + c1 * t1.y + c2 * t2.y};
+    const V m2 = V{a[0].x + c2 * t1.x + c1 * t2.x, a[0].y + c2 * t1.y + c1 * t2.y};
+    const V n1 = cmul_si<SIGN>(V{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+    const V n2 = cmul_si<SIGN>(V{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+    a[0] = cadd(a[0], cadd(t1, t2));
+    a[1] = cadd(m1, n1);
+    a[4] = csub(m1, n1);
+    a[2] = cadd(m2, n2);
+    a[3] = csub(m2, n2);
+  }
+};
+
 // multiply by exp(SIGN i pi k / 4) for k = 1, 3 (k = 2 is SIGN i)
 template <int SIGN, typename V> __device__ __forceinline__ V rot8_1(V o) {
   using R = decltype(o.x);
@@ -157,12 +183,13 @@ template <int SIGN, typename V> struct Dft<16, SIGN, V> {
 };
 
 // ---------------------------------------------------------------------------
-// radix plan: stage radices from {16, 8, 4, 3, 2}, each dividing E
+// radix plan: stage radices from {16, 8, 4, 5, 3, 2}, each dividing E
 // ---------------------------------------------------------------------------
 constexpr int pick_radix(int rem, int E) {
   return (rem % 16 == 0 && E % 16 == 0) ? 16
          : (rem % 8 == 0 && E % 8 == 0) ? 8
          : (rem % 4 == 0 && E % 4 == 0) ? 4
+         : (rem % 5 == 0 && E % 5 == 0) ? 5
          : (rem % 3 == 0 && E % 3 == 0) ? 3
          : (rem % 2 == 0 && E % 2 == 0) ? 2
                                         : 0;
@@ -170,9 +197,12 @@ constexpr int pick_radix(int rem, int E) {
 
 // elements per thread for a line of length L (radix-16 stages for 128 and
 // 256 points; 8 elements elsewhere, so that long lines keep their register
-// footprint low and use 2 or 4 wavefronts with block barriers)
+// footprint low and use 2 or 4 wavefronts with block barriers; lengths with
+// a factor 5 take 20 or 10, which hold the radices 4, 5 and 2 of 50, 80,
+// 100 and 160)
 constexpr int default_E(int L) {
-  return (L % 3 == 0) ? (L >= 24 ? 24 : L)
+  return (L % 5 == 0) ? ((L % 20 == 0) ? 20 : 10)
+         : (L % 3 == 0) ? (L >= 24 ? 24 : L)
          : (L <= 16)  ? L
          : (L == 128) ? 16
                                   : 8;
@@ -188,6 +218,11 @@ template <typename V> struct LineLds {
   int rs;
   __device__ __forceinline__ V& operator[](int i) const { return base[lpad(i) * rs]; }
 };
+
+// The T threads of a line lie in one wavefront when T divides 64 (lines of a
+// block start at multiples of T); otherwise a line may straddle two
+// wavefronts and its exchanges need block barriers.
+__host__ __device__ constexpr bool line_in_wave(int T) { return T <= 64 && 64 % T == 0; }
 
 // Ordering of an LDS exchange among the threads of one line.
 template <bool WAVE> __device__ __forceinline__ void line_sync() {
@@ -219,6 +254,11 @@ __device__ __forceinline__ void stage_twiddles(V (&w)[R], const V* __restrict__ 
     w[1] = ld(idx);
     w[2] = ld(2 * idx);
     w[3] = cmul(w[1], w[2]);
+  } else if constexpr (R == 5) {
+    w[1] = ld(idx);
+    w[2] = ld(2 * idx);
+    w[3] = cmul(w[1], w[2]);
+    w[4] = cmul(w[2], w[2]);
   } else if constexpr (R == 8) {
     w[1] = ld(idx);
     w[2] = ld(2 * idx);
@@ -255,7 +295,7 @@ struct Stages {
   static constexpr int T = L / E;
   static constexpr int Q = E / R;
   static constexpr bool LAST = (Ls * R == L);
-  static constexpr bool WAVE = (T <= 64);
+  static constexpr bool WAVE = line_in_wave(T);
 
   __device__ __forceinline__ static void run(V (&v)[E], LineLds<V> lds, int t, const V* __restrict__ tw) {
 #pragma unroll
@@ -300,9 +340,9 @@ struct Stages<L, E, L, SIGN, V> {
 
 // Unnormalised DFT of the line held as v[e] = x[t + T e]; afterwards
 // v[e] = X[t + T e].  SIGN = -1 forward, +1 inverse.  `tw` is the length-L
-// table exp(-2 pi i m / L).  With more than 64 threads per line every thread
-// of the block must call it (block barriers); otherwise every lane of the
-// line's wavefront must.
+// table exp(-2 pi i m / L).  When the line's threads do not lie in one
+// wavefront (line_in_wave) every thread of the block must call it (block
+// barriers); otherwise every lane of the line's wavefront must.
 template <int L, int E, int SIGN, typename V>
 __device__ __forceinline__ void line_fft(V (&v)[E], LineLds<V> lds, int t, const V* __restrict__ tw) {
   Stages<L, E, 1, SIGN, V>::run(v, lds, t, tw);

@@ -71,6 +71,7 @@ struct LinePassArgs {
   const double* in;
   double* out;
   int nx, ny, nt;
+  int L;  // embedding length of the transformed axis (x-pass: of nx, y-pass: of ny), >= 2n
   // spectral multipliers of the embedding circulants (length 2n, complex)
   const double2* lamA;  // constant coefficients: combined operator; variable: G
   const double2* lamB;  // variable coefficients: G^T (unused otherwise)
@@ -93,6 +94,12 @@ struct LinePassArgs {
   int col_coef;          // y-pass: coefficients constant along every y-line; column x
                          // takes d+[x], d-[x] (row 0 of the planes) inside the multiplier
 };
+
+// Embedding lengths longer than 2n: for axis lengths whose 2n is not an FFT
+// length of the line passes (n = 50, 80, 100, 160), the next one that is.
+__host__ __device__ constexpr bool padded_embedding(int L) {
+  return L == 128 || L == 192 || L == 256 || L == 384;
+}
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_xpass(const LinePassArgs& a, bool transpose, bool varcoef, hipStream_t s, int* nblocks);

@@ -20,12 +20,27 @@ std::string fmt(const char* f, double a) {
 }  // namespace
 
 bool length_supported(int n) {
-  // n = 2^a 3^b with b <= 1 and 4 <= n <= 1024 (FFT radices 2/4/8 and one 3)
+  // n = 2^a 3^b with b <= 1 and 4 <= n <= 1024 (FFT radices 2/4/8 and one 3),
+  // or one of the lengths with a factor 5 of the paper's grids (50, 80, 100)
+  // and 160
+  if (n == 50 || n == 80 || n == 100 || n == 160) return true;
   if (n < 4 || n > 1024) return false;
   int m = n;
   if (m % 3 == 0) m /= 3;
   while (m % 2 == 0) m /= 2;
   return m == 1;
+}
+
+int embed_length(int n) {
+  // the circulant embedding needs L >= 2n - 1; the line passes transform
+  // lengths 2^a 3^b (b <= 1), so the lengths with a factor 5 take the next one
+  switch (n) {
+    case 50: return 128;
+    case 80: return 192;
+    case 100: return 256;
+    case 160: return 384;
+    default: return 2 * n;
+  }
 }
 
 int validate_params(const fde_admm_params* q, std::string* msg) {
@@ -74,7 +89,7 @@ int validate(const fde_problem* p, const fde_admm_params* q, std::string* msg) {
   for (int i = 0; i < 3; ++i) {
     if (!length_supported(dims[i])) {
       *msg = std::string(names[i]) + "=" + std::to_string(dims[i]) +
-             " unsupported: need 2^a*3^b (b <= 1) between 4 and 1024";
+             " unsupported: need 2^a*3^b (b <= 1) between 4 and 1024, or 50, 80, 100, 160";
       return FDE_EINVAL;
     }
   }
@@ -194,8 +209,9 @@ void build_axis(int n, double h, double order, double dp, double dm, bool var, A
   ax->c = -1.0 / (2.0 * std::cos(order * kPi / 2.0)) / std::pow(h, order);  // eq. (4.7)
   ax->g = grunwald_weights(order, n);
   ax->dg = grunwald_weight_derivs(order, n);
-  const int L = 2 * n;
-  // first column of the 2n circulant embedding G: (g_1, .., g_n, 0, .., 0, g_0)
+  const int L = embed_length(n);
+  ax->L = L;
+  // first column of the L-point circulant embedding of G: (g_1, .., g_n, 0, .., 0, g_0)
   auto embed = [&](const std::vector<double>& gg) {
     std::vector<cd> col(L, cd(0, 0));
     for (int k = 0; k < n; ++k) col[k] = gg[k + 1];
@@ -312,8 +328,9 @@ int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::s
   s->tchan_t = tchan_eigs(s->ct, tn);  // T. Chan column c_i = (n - i) t_i / n
   s->tw_t = twiddles(p->nt);
   if (s->frac_t) {
-    // 2nt circulant embedding of C_t: first column (c_0 .. c_{nt-1}, 0 .. 0)
-    const int L = 2 * p->nt;
+    // circulant embedding of C_t (length L >= 2nt): first column (c_0 .. c_{nt-1}, 0 .. 0)
+    const int L = embed_length(p->nt);
+    s->Lt = L;
     std::vector<cd> col(L, cd(0, 0));
     for (int k = 0; k < p->nt; ++k) col[k] = s->ct[k];
     const std::vector<cd> lam = dft(col);

@@ -16,13 +16,14 @@ using cd = std::complex<double>;
 
 struct AxisTables {
   int n = 0;
+  int L = 0;                           // embedding length of the line passes (2n, or longer)
   double h = 0, order = 0, c = 0;      // mesh size, fractional order, c_a / h^a
   std::vector<double> g, dg;           // weights g_0..g_n and d g_k / d a
-  std::vector<cd> lamG, lamGT;         // 2n embedding eigenvalues of G, G^T, scaled by c/(2n)
+  std::vector<cd> lamG, lamGT;         // L-point embedding eigenvalues of G, G^T, scaled by c/L
   std::vector<cd> lamFwd, lamTr;       // constant-coefficient combined operator (mean coeffs)
   std::vector<cd> dopA, dopB;          // d L_a / d a: variable coeffs (G-part, G^T-part), else combined in A
   std::vector<cd> tchan;               // T. Chan eigenvalues (length n) of the mean operator
-  std::vector<cd> tw_emb, tw;          // twiddles exp(-2 pi i m / L) for L = 2n and L = n
+  std::vector<cd> tw_emb, tw;          // twiddles exp(-2 pi i m / L') for L' = L and L' = n
 };
 
 struct Setup {
@@ -39,12 +40,14 @@ struct Setup {
   bool frac_t = false;                 // alpha_t < 1: the time term is its own line pass
   std::vector<double> ct;              // first column of the time matrix (length nt)
   std::vector<cd> tchan_t, tw_t;       // time T. Chan eigenvalues, twiddles (length nt)
-  std::vector<cd> lam_t, lam_tT, tw_t_emb;  // 2nt embedding eigenvalues of C_t, C_t^T (with 1/(2nt)), twiddles
+  int Lt = 0;                          // embedding length along t (fractional order)
+  std::vector<cd> lam_t, lam_tT, tw_t_emb;  // Lt-point embedding eigenvalues of C_t, C_t^T (with 1/Lt), twiddles
   std::vector<double> wts, My, Mu, Mp, invMp;  // per time slice
   std::vector<double> dplus, dminus;   // (ny*nx) copies when var
 };
 
 bool length_supported(int n);
+int embed_length(int n);  // FFT length of the Toeplitz line passes along an axis of n nodes
 int validate(const fde_problem* p, const fde_admm_params* q, std::string* msg);
 int validate_params(const fde_admm_params* q, std::string* msg);
 int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::string* msg);

@@ -38,6 +38,12 @@ template <typename TS> struct PreTypes {
   using V = cplx<TS>;
 };
 
+// x-direction passes: LPB = kPreThreads / T line pairs per block; when T does
+// not divide the block (T = 5 for 50 and 100 points) the remaining threads
+// form a spare group that runs the transforms (block barriers) on LDS of its
+// own and touches no field
+constexpr int pre_x_groups(int T) { return kPreThreads / T + (kPreThreads % T ? 1 : 0); }
+
 // ---------------------------------------------------------------------------
 // pass 1: x-direction real-to-complex
 // ---------------------------------------------------------------------------
@@ -48,13 +54,13 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   constexpr int T = L / E;
   constexpr int LPB = kPreThreads / T;
   constexpr int H = L / 2 + 1;
-  __shared__ V lds[LPB * lpad_size(L)];
+  __shared__ V lds[pre_x_groups(T) * lpad_size(L)];
   if (a.done && *a.done) return;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int nlines = a.ny * a.nt;
   const int pair = blockIdx.x * LPB + g;
   const int l0 = 2 * pair, l1 = 2 * pair + 1;
-  const bool h0 = l0 < nlines, h1 = l1 < nlines;
+  const bool h0 = g < LPB && l0 < nlines, h1 = g < LPB && l1 < nlines;
   LineLds<V> buf{lds + g * lpad_size(L), 1};
   const V* tw = reinterpret_cast<const V*>(a.twx);
 
@@ -334,13 +340,13 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
   constexpr int T = L / E;
   constexpr int LPB = kPreThreads / T;
   constexpr int H = L / 2 + 1;
-  __shared__ V lds[LPB * lpad_size(L)];
+  __shared__ V lds[pre_x_groups(T) * lpad_size(L)];
   if (a.done && *a.done) return;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int nlines = a.ny * a.nt;
   const int pair = blockIdx.x * LPB + g;
   const int l0 = 2 * pair, l1 = 2 * pair + 1;
-  const bool h0 = l0 < nlines, h1 = l1 < nlines;
+  const bool h0 = g < LPB && l0 < nlines, h1 = g < LPB && l1 < nlines;
   LineLds<V> buf{lds + g * lpad_size(L), 1};
   const V* tw = reinterpret_cast<const V*>(a.twx);
   const V* spec = reinterpret_cast<const V*>(a.spec);
@@ -405,8 +411,9 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
-#define FDE_FOR_DIM_LENGTHS(X) \
-  X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define FDE_FOR_DIM_LENGTHS(X)                                                                          \
+  X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(50) X(64) X(80) X(96) X(100) X(128) X(160) X(192) X(256) \
+  X(384) X(512) X(768) X(1024)
 
 template <int L, typename TS>
 static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) {

@@ -24,13 +24,17 @@ constexpr int kLineThreads = 256;
 // ---------------------------------------------------------------------------
 // x-pass: contiguous lines (t, j), with the time difference fused
 // ---------------------------------------------------------------------------
-template <int L, bool VAR, bool TRANS>
+// PAD: the embedding is longer than 2n (L >= 2n, the length n read at run
+// time): elements n..L/2-1 of the data half are zero and only the first n
+// results are kept.  Without PAD, n = L/2 is known at compile time.
+template <int L, bool VAR, bool TRANS, bool PAD = false>
 __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   constexpr int E = default_E(L);
   constexpr int T = L / E;
   static_assert(T <= kLineThreads, "line too long for one block");
+  static_assert(kLineThreads % T == 0, "whole lines per block");
   constexpr int LPB = kLineThreads / T;  // packed line pairs per block
-  constexpr int n = L / 2;
+  const int n = PAD ? a.nx : L / 2;
   __shared__ double2 lds[LPB * lpad_size(L)];
   if (a.done && *a.done) return;
 
@@ -42,22 +46,23 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   LineLds<double2> buf{lds + g * lpad_size(L), 1};
   const double* __restrict__ in = a.in;
 
-  // element e of thread t is i = t + T e; i < n exactly when e < EH, so the
+  // element e of thread t is i = t + T e; i < L/2 exactly when e < EH, so the
   // zero half of the embedding and the discarded half of the result are
-  // known at compile time
+  // known at compile time (with PAD, i < n is checked as well)
   constexpr int EH = E / 2;
   double2 v[E];
   double2 w[E];
 #pragma unroll
   for (int e = 0; e < EH; ++e) {
     const int i = t + T * e;
+    const bool in_line = !PAD || i < n;
     double x0 = 0.0, x1 = 0.0;
-    if (h0) x0 = in[(size_t)l0 * n + i];
-    if (h1) x1 = in[(size_t)l1 * n + i];
+    if (h0 && in_line) x0 = in[(size_t)l0 * n + i];
+    if (h1 && in_line) x1 = in[(size_t)l1 * n + i];
     if constexpr (VAR && TRANS) {
       double p0 = 0, p1 = 0, m0 = 0, m1 = 0;
-      if (h0) { p0 = a.dplus[(l0 % a.ny) * n + i]; m0 = a.dminus[(l0 % a.ny) * n + i]; }
-      if (h1) { p1 = a.dplus[(l1 % a.ny) * n + i]; m1 = a.dminus[(l1 % a.ny) * n + i]; }
+      if (h0 && in_line) { p0 = a.dplus[(l0 % a.ny) * n + i]; m0 = a.dminus[(l0 % a.ny) * n + i]; }
+      if (h1 && in_line) { p1 = a.dplus[(l1 % a.ny) * n + i]; m1 = a.dminus[(l1 % a.ny) * n + i]; }
       v[e] = double2{p0 * x0, p1 * x1};
       w[e] = double2{m0 * x0, m1 * x1};
     } else {
@@ -93,16 +98,17 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   // lines (16-byte accesses; n is even) and issues all loads of a group of
   // element pairs before its first store.  Missing lines and time neighbours
   // read an address inside the field and are zeroed after the load.
-  constexpr bool WAVE = T <= 64;
+  constexpr bool WAVE = line_in_wave(T);
+  constexpr int NH = L / 2;  // offset of the second product (G^T v) in the buffer
   line_sync<WAVE>();
 #pragma unroll
   for (int e = 0; e < EH; ++e) {
     buf[t + T * e] = v[e];
-    if constexpr (VAR && !TRANS) buf[t + T * e + n] = w[e];
+    if constexpr (VAR && !TRANS) buf[t + T * e + NH] = w[e];
   }
   line_sync<WAVE>();
 
-  constexpr int KE = E / 4;                    // element pairs per thread (n / 2 = T E / 4)
+  constexpr int KE = E / 4;                    // element pairs per thread (L / 4 = T E / 4)
   constexpr int KG = (KE % 2 == 0) ? 2 : KE;   // element pairs per load group
   const size_t plane = (size_t)a.ny * n;
   const int tt0 = l0 / a.ny, tt1 = l1 / a.ny;
@@ -119,7 +125,7 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
     double2 c0[KG], c1[KG], p0[KG], p1[KG], dp0[KG], dp1[KG], dm0[KG], dm1[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
-      const int i = 2 * (t + T * (k0 + k));
+      const int i = (!PAD || 2 * (t + T * (k0 + k)) < n) ? 2 * (t + T * (k0 + k)) : 0;
       c0[k] = c1[k] = p0[k] = p1[k] = z2;
       if (timed) {
         c0[k] = ld2(in + b0 + i);
@@ -137,10 +143,11 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
       const int i = 2 * (t + T * (k0 + k));
+      if (PAD && i >= n) continue;
       const double2 sa = buf[i], sb = buf[i + 1];
       double2 s0{sa.x, sb.x}, s1{sa.y, sb.y};  // spatial products of lines l0, l1
       if constexpr (VAR && !TRANS) {
-        const double2 ta = buf[i + n], tb = buf[i + n + 1];
+        const double2 ta = buf[i + NH], tb = buf[i + NH + 1];
         s0 = double2{dp0[k].x * s0.x + dm0[k].x * ta.x, dp0[k].y * s0.y + dm0[k].y * tb.x};
         s1 = double2{dp1[k].x * s1.x + dm1[k].x * ta.y, dp1[k].y * s1.y + dm1[k].y * tb.y};
       }
@@ -178,12 +185,14 @@ template <int L, int S = 0> struct YCfg {
 // The two real columns packed in Z = F(u0 + i u1) get M_0 u0 + i M_1 u1 from one
 // inverse transform of ((l_0 + l_1)/2) Z[k] + ((l_0 - l_1)/2) conj Z[L-k]
 // (Hermitian separation), so a pair costs two transforms instead of three.
-template <int L, bool VAR, bool TRANS, int S, bool COL = false>
+// PAD: as for the x-pass, an embedding longer than 2n (n = ny read at run time).
+template <int L, bool VAR, bool TRANS, int S, bool COL = false, bool PAD = false>
 __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   static_assert(!(VAR && COL), "per-column coefficients use the constant-coefficient tile path");
   using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
-  constexpr int n = L / 2;
+  constexpr int NH = L / 2;  // rows of the data half; the second input (d- v) starts there
+  const int n = PAD ? a.ny : NH;
   constexpr int TX = 2 * P;
   __shared__ double2 lds[lpad_size(L) * RS];
   if (a.done && *a.done) return;
@@ -207,9 +216,9 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   // tile's first pair (always inside) and are zeroed after the load, so a
   // thread issues all its loads before the first LDS store, without branches.
   // Rows 0..n-1 hold v (d+ v in the transposed variable case, with d- v in
-  // rows n..2n-1); columns beyond nx are zero.
-  constexpr int NE = n * P;
-  constexpr int KL = (NE + NT - 1) / NT;
+  // rows NH..NH+n-1); columns beyond nx are zero.
+  const int NE = n * P;
+  constexpr int KL = (NH * P + NT - 1) / NT;
   int ge[KL];     // offset of the element within the slice (plane index)
   bool ok[KL];
 #pragma unroll
@@ -238,7 +247,7 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
         const double2 v0 = ok[k] ? lv[k] : double2{0.0, 0.0};
         if constexpr (VAR && TRANS) {
           lds[lpad(row) * RS + cp] = double2{lp[k].x * v0.x, lp[k].y * v0.y};
-          lds[lpad(row + n) * RS + cp] = double2{lm[k].x * v0.x, lm[k].y * v0.y};
+          lds[lpad(row + NH) * RS + cp] = double2{lm[k].x * v0.x, lm[k].y * v0.y};
         } else {
           lds[lpad(row) * RS + cp] = v0;
         }
@@ -247,16 +256,17 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   }
   __syncthreads();
 
-  // element e of thread t is row i = t + T e; i < n exactly when e < EH
+  // element e of thread t is row i = t + T e; i < L/2 exactly when e < EH
+  // (with PAD, rows n..L/2-1 hold no data and are read as zero)
   constexpr int EH = E / 2;
   double2 v[E];
   double2 w[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     v[e] = w[e] = double2{0.0, 0.0};
-    if (e < EH) {
+    if (e < EH && (!PAD || t + T * e < n)) {
       v[e] = buf[t + T * e];
-      if constexpr (VAR && TRANS) w[e] = buf[t + T * e + n];
+      if constexpr (VAR && TRANS) w[e] = buf[t + T * e + NH];
     }
   }
   __syncthreads();
@@ -265,7 +275,7 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   if constexpr (VAR && TRANS) line_fft<L, E, -1>(w, buf, t, a.tw);
   if constexpr (COL) {
     // partner Z[(L - i) mod L] through the pair's LDS stripe
-    constexpr bool WAVE = T <= 64;
+    constexpr bool WAVE = line_in_wave(T);
     line_sync<WAVE>();
 #pragma unroll
     for (int e = 0; e < E; ++e) buf[t + T * e] = v[e];
@@ -309,7 +319,7 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 #pragma unroll
     for (int e = 0; e < EH; ++e) {
       buf[t + T * e] = v[e];
-      if constexpr (VAR && !TRANS) buf[t + T * e + n] = w[e];
+      if constexpr (VAR && !TRANS) buf[t + T * e + NH] = w[e];
     }
   }
   __syncthreads();
@@ -327,7 +337,7 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
       const int li = ok[k] ? lpad(idx / P) * RS + idx % P : 0;
       sp[k] = lds[li];
       if constexpr (VAR && !TRANS) {
-        const double2 s2 = lds[ok[k] ? lpad(idx / P + n) * RS + idx % P : 0];
+        const double2 s2 = lds[ok[k] ? lpad(idx / P + NH) * RS + idx % P : 0];
         const double2 dp = ld2(a.dplus + ge[k]), dm = ld2(a.dminus + ge[k]);
         sp[k] = double2{dp.x * sp[k].x + dm.x * s2.x, dp.y * sp[k].y + dm.y * s2.y};
       }
@@ -377,6 +387,17 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 
+template <int L, bool PAD>
+static void xpass_launch(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int blocks) {
+  if (var) {
+    if (tr) launch_pass(k_xpass<L, true, true, PAD>, blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, true, false, PAD>, blocks, kLineThreads, s, a);
+  } else {
+    if (tr) launch_pass(k_xpass<L, false, true, PAD>, blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, false, false, PAD>, blocks, kLineThreads, s, a);
+  }
+}
+
 template <int L>
 static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
   constexpr int E = default_E(L);
@@ -385,14 +406,32 @@ static hipError_t xpass_L(const LinePassArgs& a, bool tr, bool var, hipStream_t 
   const int pairs = (nlines + 1) / 2;
   const int blocks = (pairs + LPB - 1) / LPB;
   if (nb) *nb = blocks;
-  if (var) {
-    if (tr) launch_pass(k_xpass<L, true, true>, blocks, kLineThreads, s, a);
-    else launch_pass(k_xpass<L, true, false>, blocks, kLineThreads, s, a);
+  if (2 * a.nx == L) {
+    xpass_launch<L, false>(a, tr, var, s, blocks);
   } else {
-    if (tr) launch_pass(k_xpass<L, false, true>, blocks, kLineThreads, s, a);
-    else launch_pass(k_xpass<L, false, false>, blocks, kLineThreads, s, a);
+    if constexpr (padded_embedding(L)) {
+      if (2 * a.nx > L) return hipErrorInvalidValue;
+      xpass_launch<L, true>(a, tr, var, s, blocks);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
+}
+
+template <int L, int S, bool PAD>
+static void ypass_launch(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int blocks) {
+  using C = YCfg<L, S>;
+  if (a.col_coef) {
+    if (tr) launch_pass(k_ypass<L, false, true, S, true, PAD>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S, true, PAD>, blocks, C::NT, s, a);
+  } else if (var) {
+    if (tr) launch_pass(k_ypass<L, true, true, S, false, PAD>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, true, false, S, false, PAD>, blocks, C::NT, s, a);
+  } else {
+    if (tr) launch_pass(k_ypass<L, false, true, S, false, PAD>, blocks, C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S, false, PAD>, blocks, C::NT, s, a);
+  }
 }
 
 template <int L, int S>
@@ -401,15 +440,15 @@ static hipError_t ypass_LS(const LinePassArgs& a, bool tr, bool var, hipStream_t
   const int tiles = (a.nx + 2 * C::P - 1) / (2 * C::P);
   const int blocks = tiles * a.nt;
   if (nb) *nb = blocks;
-  if (a.col_coef) {
-    if (tr) launch_pass(k_ypass<L, false, true, S, true>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, false, false, S, true>, blocks, C::NT, s, a);
-  } else if (var) {
-    if (tr) launch_pass(k_ypass<L, true, true, S>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, true, false, S>, blocks, C::NT, s, a);
+  if (2 * a.ny == L) {
+    ypass_launch<L, S, false>(a, tr, var, s, blocks);
   } else {
-    if (tr) launch_pass(k_ypass<L, false, true, S>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, false, false, S>, blocks, C::NT, s, a);
+    if constexpr (padded_embedding(L)) {
+      if (2 * a.ny > L) return hipErrorInvalidValue;
+      ypass_launch<L, S, true>(a, tr, var, s, blocks);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
@@ -434,7 +473,7 @@ int ypass_tile_width(int L, int variant) {
 }
 
 hipError_t launch_xpass(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
-  switch (2 * a.nx) {
+  switch (a.L) {
 #define CASE(Lv) case Lv: return xpass_L<Lv>(a, tr, var, s, nb);
     FDE_FOR_EMBED_LENGTHS(CASE)
 #undef CASE
@@ -444,7 +483,7 @@ hipError_t launch_xpass(const LinePassArgs& a, bool tr, bool var, hipStream_t s,
 }
 
 hipError_t launch_ypass(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int* nb) {
-  switch (2 * a.ny) {
+  switch (a.L) {
 #define CASE(Lv) case Lv: return ypass_L<Lv>(a, tr, var, s, nb);
     FDE_FOR_EMBED_LENGTHS(CASE)
 #undef CASE

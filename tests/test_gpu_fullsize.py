@@ -24,7 +24,8 @@ def tuned_context(w, **kw):
 
 
 def max_rel(a, b):
-    return float(np.max(np.abs(a - b))) / float(np.max(np.abs(b)))
+    nb = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b))) / (nb if nb > 0 else 1.0)
 
 
 @pytest.fixture(scope="module")

@@ -50,12 +50,19 @@ def make(kind):
         return var_fields(W.small(nx=4, ny=4, nt=4).replace(alpha=1.7, beta=1.3))
     if kind == "min_mixed_4x6x12":
         return W.small(nx=4, ny=6, nt=12).replace(alpha=1.2, beta=1.9)
+    # lengths with a factor 5: radix-5 preconditioner transforms, longer operator embeddings
+    if kind == "radix5_var_50x80x100":
+        return var_fields(W.small(nx=50, ny=80, nt=100).replace(alpha=1.35, beta=1.65))
+    if kind == "radix5_160x100x50":
+        return W.small(nx=160, ny=100, nt=50).replace(alpha=1.8, beta=1.2)
+    if kind == "radix5_colcoef_100x50x8":
+        return W.headline(nx=100, ny=50, nt=8)
     raise KeyError(kind)
 
 
 OP_CASES = ["small", "headline_24x16x8", "ragged_var_24x48x6", "const_96x12x4", "tiny_var_6x8x4",
             "laplace_48x24x6", "radix3_192x96x12", "long_1024x8x4", "tall_8x1024x4", "min_4x4x4",
-            "min_mixed_4x6x12"]
+            "min_mixed_4x6x12", "radix5_var_50x80x100", "radix5_160x100x50", "radix5_colcoef_100x50x8"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -81,7 +88,7 @@ def test_apply_A(kind, transpose):
 
 
 @pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "ragged_var_24x48x6", "radix3_192x96x12",
-                                  "min_4x4x4"])
+                                  "min_4x4x4", "radix5_var_50x80x100", "radix5_colcoef_100x50x8"])
 def test_apply_S(kind):
     banner("apply_S", kind)
     w = make(kind).replace(rho=1.3, delta=0.6, obj_weights=1)
@@ -115,7 +122,8 @@ def test_precond(kind, fp32):
     assert rel(got, ref) <= tol, rel(got, ref)
 
 
-@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "radix3_192x96x12", "min_4x4x4", "min_mixed_4x6x12"])
+@pytest.mark.parametrize("kind", ["small", "headline_24x16x8", "radix3_192x96x12", "min_4x4x4", "min_mixed_4x6x12",
+                                  "radix5_var_50x80x100", "radix5_160x100x50"])
 def test_krylov(kind):
     banner("krylov", kind)
     w = make(kind)

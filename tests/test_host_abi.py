@@ -75,10 +75,10 @@ def test_negative_coefficient_rejected():
 
 def test_supported_sizes():
     w = W.small()
-    for n in (4, 6, 8, 12, 16, 24, 48, 96, 192, 256, 384, 512, 768, 1024):
+    for n in (4, 6, 8, 12, 16, 24, 48, 50, 80, 96, 100, 160, 192, 256, 384, 512, 768, 1024):
         prob, prm = fde.from_workload(w.replace(nx=n, ny=n, nt=n, yhat=None))
         fde.validate(prob, prm)
-    for n in (3, 5, 9, 18, 36, 1536, 2048):
+    for n in (3, 5, 9, 10, 18, 20, 36, 40, 200, 1536, 2048):
         prob, prm = fde.from_workload(w.replace(nx=n, yhat=None))
         with pytest.raises(fde.FdeError):
             fde.validate(prob, prm)
