@@ -134,12 +134,13 @@ def kernel_source_hash(pass_name):
     return h.hexdigest()
 
 
-def measured_traffic(pass_name, tile_width):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary profiles/traffic_<pass>_headline_256x256x64.json (FETCH_SIZE and
-    WRITE_SIZE passes scaled by the copy kernel), or None when there is none
-    for this pass (and y-pass tile width) or the kernel sources have changed
-    since the counters were taken."""
+def measured_traffic(pass_name, tile_width=None):
+    """Memory-side bytes per launch of the dominant kernel from the committed
+    counter summary profiles/traffic_<pass>_headline_256x256x64.json
+    (FETCH_SIZE and WRITE_SIZE runs scaled by the copy kernel; they count the
+    L2's traffic to the memory side, last-level cache hits included), or None
+    when there is none for this pass or the kernel sources have changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{pass_name}_headline_256x256x64.json")
     try:
         with open(path) as fh:
@@ -147,8 +148,6 @@ def measured_traffic(pass_name, tile_width):
     except (OSError, ValueError):
         return None
     if rec.get("pass") != pass_name or rec.get("source_sha256") != kernel_source_hash(pass_name):
-        return None
-    if pass_name.startswith("ypass") and rec.get("tile_width") != tile_width:
         return None
     return rec.get("traffic_bytes")
 
