@@ -347,8 +347,17 @@ fde_status fde_autotune(fde_ctx* ctx, int32_t* choices);
  * all of them as resumable state machines, polling a HIP event per instance
  * and enqueueing its next phase as soon as the previous one has finished,
  * so the instances' kernels overlap on the GPU and no instance waits for
- * another's host synchronisation.  concurrent = 0 runs the same solves one
- * after the other (the sequential reference).
+ * another's host synchronisation (concurrent = 1).  concurrent = 0 runs the
+ * same solves one after the other (the sequential reference).
+ * concurrent = 2 (lockstep): the PCG iterations of all instances run as
+ * batched launches, one launch per pass kind and position covering every
+ * instance's blocks (each instance keeps its own tables, block decomposition
+ * and done flag), the other ADMM phases as each instance's own launches; the
+ * instances advance one ADMM iteration at a time together.  Instances whose
+ * x-step has no batched form (MINRES, a fractional time order, lengths
+ * without batched pass variants) make the call run the concurrent mode
+ * instead.  Results equal the single solves' up to the order of the partial
+ * sums in the fused dot products (a few units in the last place).
  * Arrays indexed by instance: yhat[i], g[i] (g may be NULL, or g[i] NULL),
  * and the iterate fields y[i] .. wu[i] (device fields of instance i's size,
  * read as the starting point, overwritten).  The caller makes the inputs

@@ -30,6 +30,7 @@ using fde::host::cd;
 
 namespace fde {
 thread_local PassEventQueue t_pass_events;
+thread_local std::vector<RecordedPass>* t_record = nullptr;
 }
 
 namespace {
@@ -554,6 +555,7 @@ struct KrylovRun {
   int iters = 0;
   double relres = 0;
   fde_status status = FDE_OK;
+  bool defer = false;  // batched solves: the set-up only; the iterations come from the batch
 };
 
 // How krylov_begin forms S x for the initial residual: a full apply (SX_APPLY);
@@ -591,6 +593,7 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
   a.scal_w = c->scal;
   a.ints = c->ints;
   HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
+  if (kr->defer) return FDE_OK;
   if (c->use_graph && !c->ptime) {
     const fde_status st = ensure_pcg_graph(c, x);
     if (st != FDE_OK) return st;
@@ -839,6 +842,7 @@ struct AdmmRun {
   int predict = 0;
   bool have_byp = false;  // c->fw holds M_p^{-1} B y for the current y
   bool have_rhs = false;  // the update pass already wrote this iteration's Ru, r, v, c
+  bool batched = false;   // lockstep batch: Krylov iterations come from batched launches
   double prev_min = 0.0;
   double t0 = 0, tp = 0, t_pcg = 0;
   KrylovRun kr;
@@ -882,15 +886,17 @@ fde_status admm_enqueue_iteration(fde_ctx* c, AdmmRun* R) {
   R->tp = now();
   R->phase = PH_PCG;
   HIP_TRY(hipEventRecord(c->ph_ev[1], c->stream));
+  R->kr.defer = R->batched;
   return krylov_begin(c, c->bvec, R->f.y, tol, q.krylov_maxit, R->predict, &R->kr, sx);
 }
 
 fde_status admm_begin(fde_ctx* c, AdmmRun* R, const double* yhat, const double* g, double* y, double* u, double* zy,
-                      double* zu, double* p, double* wy, double* wu) {
+                      double* zu, double* p, double* wy, double* wu, bool batched = false) {
   CHECK_ALIGNED("fde_admm_solve", yhat, g, y, u, zy, zu, p, wy, wu);
   const auto& s = c->su;
   const fde_admm_params& q = c->prm;
   *R = AdmmRun{};
+  R->batched = batched;
   R->t0 = now();
   fde::AdmmConsts& k = R->k;
   k.n = c->N;
@@ -1600,13 +1606,190 @@ fde_status fde_admm_solve(fde_ctx* ctx, const double* yhat, const double* g, dou
 struct fde_batch {
   std::vector<fde_ctx*> ctx;
   std::vector<hipStream_t> streams;
+  hipStream_t lockstep = nullptr;  // the one stream of the lockstep mode
 };
 
 namespace {
 void batch_free(fde_batch* b) {
   for (fde_ctx* c : b->ctx) fde_destroy(c);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->lockstep) (void)hipStreamDestroy(b->lockstep);
   delete b;
+}
+
+// ---------------------------------------------------------------------------
+// Lockstep batch: the PCG iterations of all instances as batched pass
+// launches.  Each instance's PCG iteration is recorded once (its pass
+// launches captured, not issued); the passes at each position are grouped by
+// kernel and issued as one launch per group over a table of the instances'
+// arguments (BatchArgs), each instance keeping its own block decomposition.
+// Iterations after an instance's convergence return at once (its device done
+// flag), as in the single solve.
+// ---------------------------------------------------------------------------
+struct PassGroup {
+  const void* kern = nullptr;
+  int threads = 0, blocks = 0, count = 0;
+  const void* args = nullptr;  // device table of the instances' arguments
+  const int* first = nullptr;  // device prefix sums of their block counts
+};
+
+struct BatchPcg {
+  std::vector<std::vector<PassGroup>> pos;  // per pass position, its kernel groups
+  void* dev = nullptr;                      // one allocation: tables, ints pointers, flags
+  const int* const* ints = nullptr;
+  int* flags = nullptr;
+  int* h_flags = nullptr;  // pinned
+  hipEvent_t ev = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int count = 0;
+  int launches = 0;  // pass launches per batch iteration
+};
+
+void batch_pcg_free(BatchPcg* bp) {
+  if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
+  if (bp->graph) (void)hipGraphDestroy(bp->graph);
+  if (bp->cap) (void)hipStreamDestroy(bp->cap);
+  if (bp->ev) (void)hipEventDestroy(bp->ev);
+  if (bp->h_flags) (void)hipHostFree(bp->h_flags);
+  if (bp->dev) (void)hipFree(bp->dev);
+  *bp = BatchPcg{};
+}
+
+hipError_t batch_pcg_iteration(const BatchPcg* bp, hipStream_t s) {
+  for (const auto& groups : bp->pos)
+    for (const PassGroup& g : groups) {
+      fde::BatchArgs<fde::LinePassArgs> ba{static_cast<const fde::LinePassArgs*>(g.args), g.first, g.count};
+      void* kargs[] = {&ba};
+      const hipError_t e = hipLaunchKernel(g.kern, dim3(g.blocks), dim3(g.threads), kargs, 0, s);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+// Record and group the PCG iterations of the instances cs (solution fields xs);
+// FDE_EINVAL when a pass has no batched form (the caller runs another mode).
+fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<double*>& xs, BatchPcg* bp) {
+  using fde::RecordedPass;
+  const int n = (int)cs.size();
+  std::vector<std::vector<RecordedPass>> rec(n);
+  for (int i = 0; i < n; ++i) {
+    fde::t_record = &rec[i];
+    const hipError_t e = enqueue_pcg_iteration_passes(cs[i], xs[i]);
+    fde::t_record = nullptr;
+    if (e != hipSuccess) return (fde_status)fail(FDE_EHIP, std::string("batch record: ") + hipGetErrorString(e));
+  }
+  const size_t npos = rec[0].size();
+  for (int i = 0; i < n; ++i) {
+    if (rec[i].size() != npos) return (fde_status)fail(FDE_EINVAL, "batch: instances with different pass lists");
+    for (const RecordedPass& r : rec[i])
+      if (!r.batch_kernel) return (fde_status)fail(FDE_EINVAL, "batch: a pass without a batched form");
+  }
+  // layout of the device buffer: per group, its argument table and prefix table
+  struct GroupHost {
+    size_t pos;
+    const void* kern;
+    int threads, kind;
+    std::vector<int> members;
+    size_t slot = 0;  // index among its position's groups
+  };
+  std::vector<GroupHost> groups;
+  for (size_t p = 0; p < npos; ++p) {
+    const size_t g0 = groups.size();
+    for (int i = 0; i < n; ++i) {
+      const RecordedPass& r = rec[i][p];
+      size_t g = g0;
+      while (g < groups.size() && groups[g].kern != r.batch_kernel) ++g;
+      if (g == groups.size()) groups.push_back(GroupHost{p, r.batch_kernel, r.threads, r.kind, {}});
+      groups[g].members.push_back(i);
+    }
+  }
+  auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t total = 0;
+  std::vector<size_t> off_args(groups.size()), off_first(groups.size());
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const size_t asz = groups[g].kind == 0 ? sizeof(fde::LinePassArgs) : sizeof(fde::PrecondArgs);
+    off_args[g] = total;
+    total = align(total + asz * groups[g].members.size());
+    off_first[g] = total;
+    total = align(total + sizeof(int) * (groups[g].members.size() + 1));
+  }
+  const size_t off_ints = total;
+  total = align(total + sizeof(int*) * n);
+  const size_t off_flags = total;
+  total = align(total + sizeof(int) * n);
+  std::vector<unsigned char> host(total, 0);
+  bp->pos.assign(npos, {});
+  int launches = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    const GroupHost& G = groups[g];
+    const size_t asz = G.kind == 0 ? sizeof(fde::LinePassArgs) : sizeof(fde::PrecondArgs);
+    int* first = reinterpret_cast<int*>(host.data() + off_first[g]);
+    int blocks = 0;
+    for (size_t m = 0; m < G.members.size(); ++m) {
+      const RecordedPass& r = rec[G.members[m]][G.pos];
+      std::memcpy(host.data() + off_args[g] + asz * m, r.args, asz);
+      first[m] = blocks;
+      blocks += r.blocks;
+    }
+    first[G.members.size()] = blocks;
+    PassGroup pg;
+    pg.kern = G.kern;
+    pg.threads = G.threads;
+    pg.blocks = blocks;
+    pg.count = (int)G.members.size();
+    groups[g].slot = bp->pos[G.pos].size();
+    bp->pos[G.pos].push_back(pg);
+    ++launches;
+  }
+  const int** ints_host = reinterpret_cast<const int**>(host.data() + off_ints);
+  for (int i = 0; i < n; ++i) ints_host[i] = cs[i]->ints;
+  HIP_TRY(hipMalloc(&bp->dev, total));
+  HIP_TRY(hipMemcpy(bp->dev, host.data(), total, hipMemcpyHostToDevice));
+  unsigned char* d = static_cast<unsigned char*>(bp->dev);
+  for (size_t g = 0; g < groups.size(); ++g) {
+    PassGroup& pg = bp->pos[groups[g].pos][groups[g].slot];
+    pg.args = d + off_args[g];
+    pg.first = reinterpret_cast<const int*>(d + off_first[g]);
+  }
+  bp->ints = reinterpret_cast<const int* const*>(d + off_ints);
+  bp->flags = reinterpret_cast<int*>(d + off_flags);
+  bp->count = n;
+  bp->launches = launches;
+  HIP_TRY(hipHostMalloc((void**)&bp->h_flags, sizeof(int) * n, hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&bp->ev, hipEventDisableTiming));
+  // kGraphIters batch iterations captured once
+  HIP_TRY(hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < kGraphIters && e == hipSuccess; ++k) e = batch_pcg_iteration(bp, bp->cap);
+  const hipError_t e2 = hipStreamEndCapture(bp->cap, &bp->graph);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return (fde_status)fail(FDE_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+  HIP_TRY(hipGraphInstantiate(&bp->exec, bp->graph, nullptr, nullptr, 0));
+  return FDE_OK;
+}
+
+// Batch iterations until every instance's PCG done flag is set (first chunk:
+// `predict` iterations rounded up to whole graphs; then one graph at a time).
+fde_status batch_pcg_run(BatchPcg* bp, hipStream_t s, int predict, int maxit) {
+  int chunk = ((std::max(predict, 1) + kGraphIters - 1) / kGraphIters) * kGraphIters;
+  int enqueued = 0;
+  while (true) {
+    for (int k = 0; k < chunk; k += kGraphIters) HIP_TRY(hipGraphLaunch(bp->exec, s));
+    enqueued += chunk;
+    HIP_TRY(fde::launch_gather_done(bp->ints, bp->count, bp->flags, s));
+    HIP_TRY(hipMemcpyAsync(bp->h_flags, bp->flags, sizeof(int) * bp->count, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(bp->ev, s));
+    HIP_TRY(hipEventSynchronize(bp->ev));
+    bool all = true;
+    for (int i = 0; i < bp->count; ++i) all = all && bp->h_flags[i] != 0;
+    if (all) return FDE_OK;
+    // every instance stops by its own iteration limit; this is a guard only
+    if (enqueued > maxit + kGraphIters) return (fde_status)fail(FDE_EHIP, "batched PCG: done flags not set");
+    chunk = kGraphIters;
+  }
 }
 }  // namespace
 
@@ -1636,6 +1819,9 @@ fde_status fde_batch_create(int count, const fde_problem* probs, const fde_admm_
       return (fde_status)fail(st, "instance " + std::to_string(i) + ": " + msg);
     }
     b->ctx.push_back(c);
+    // the PCG convergence test rides in the y-forward pass (the batched PCG
+    // iteration has only pass launches); results are identical either way
+    c->conv_sep = 0;
     const fde_status ts = fde_autotune(c, nullptr);  // cached per shape
     if (ts != FDE_OK) {
       const std::string msg = g_err;
@@ -1652,6 +1838,112 @@ fde_status fde_batch_destroy(fde_batch* b) {
   return FDE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Lockstep mode of fde_batch_solve: every instance on one stream, phase by
+// phase; the Krylov iterations of all instances in a PCG phase as batched
+// pass launches (a graph of kGraphIters batch iterations), the other phases
+// as each instance's own launches.  FDE_EINVAL (nothing run) when an instance
+// has no batched form (MINRES x-step, a fractional time order, lengths
+// without batched twins): the caller then runs the concurrent mode.
+fde_status batch_lockstep(fde_batch* b, const double* const* yhat, const double* const* g, double* const* y,
+                          double* const* u, double* const* zy, double* const* zu, double* const* p,
+                          double* const* wy, double* const* wu, std::vector<AdmmRun>& R,
+                          std::vector<fde_status>& res) {
+  const int n = (int)b->ctx.size();
+  for (fde_ctx* c : b->ctx)
+    if (c->prm.krylov_solver != 0 || c->frac_t)
+      return (fde_status)fail(FDE_EINVAL, "lockstep batch: an instance without batched passes");
+  if (!b->lockstep) HIP_TRY(hipStreamCreateWithFlags(&b->lockstep, hipStreamNonBlocking));
+  hipStream_t ls = b->lockstep;
+  std::vector<hipStream_t> saved(n);
+  for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(b->ctx[i]->stream));
+  for (int i = 0; i < n; ++i) {
+    saved[i] = b->ctx[i]->stream;
+    b->ctx[i]->stream = ls;
+  }
+  BatchPcg bp;
+  std::vector<fde_ctx*> cs;
+  std::vector<double*> xs;
+  for (int i = 0; i < n; ++i) {
+    cs.push_back(b->ctx[i]);
+    xs.push_back(y[i]);
+  }
+  fde_status st = batch_pcg_build(cs, xs, &bp);
+  auto restore = [&]() {
+    (void)hipStreamSynchronize(ls);
+    for (int i = 0; i < n; ++i) b->ctx[i]->stream = saved[i];
+    batch_pcg_free(&bp);
+  };
+  if (st != FDE_OK) {
+    restore();
+    return st;
+  }
+  std::vector<char> live(n, 0);
+  int remaining = 0, maxit = 0;
+  for (int i = 0; i < n; ++i) {
+    res[i] = admm_begin(b->ctx[i], &R[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i],
+                        true);
+    maxit = std::max(maxit, b->ctx[i]->prm.krylov_maxit);
+    if (res[i] >= 0) {
+      live[i] = 1;
+      ++remaining;
+    }
+  }
+  auto drop = [&](int i, fde_status s2) {
+    res[i] = s2;
+    live[i] = 0;
+    --remaining;
+  };
+  while (remaining > 0) {
+    // Krylov phase of every instance that is in one, as batched iterations
+    int predict = 0;
+    bool any_pcg = false;
+    for (int i = 0; i < n; ++i)
+      if (live[i] && R[i].phase == PH_PCG) {
+        any_pcg = true;
+        predict = std::max(predict, R[i].predict);
+      }
+    if (any_pcg) {
+      st = batch_pcg_run(&bp, ls, predict, maxit);
+      if (st != FDE_OK) break;
+      for (int i = 0; i < n; ++i)
+        if (live[i] && R[i].phase == PH_PCG) {
+          const fde_status s2 = post_readback(b->ctx[i]);
+          if (s2 != FDE_OK) drop(i, s2);
+        }
+      const hipError_t he = hipStreamSynchronize(ls);
+      if (he != hipSuccess) {
+        st = (fde_status)fail(FDE_EHIP, std::string("lockstep batch: ") + hipGetErrorString(he));
+        break;
+      }
+    }
+    // each phase's completion, in the order PCG -> update -> objective
+    for (int ph : {PH_PCG, PH_RES, PH_OBJ}) {
+      bool any = false;
+      for (int i = 0; i < n; ++i) {
+        if (!live[i] || R[i].phase != ph) continue;
+        const fde_status s2 = admm_advance(b->ctx[i], &R[i]);
+        any = true;
+        if (s2 < 0) drop(i, s2);
+        else if (R[i].phase == PH_DONE) drop(i, R[i].status);
+      }
+      const hipError_t he = any ? hipStreamSynchronize(ls) : hipSuccess;
+      if (he != hipSuccess) {
+        st = (fde_status)fail(FDE_EHIP, std::string("lockstep batch: ") + hipGetErrorString(he));
+        break;
+      }
+    }
+    if (st != FDE_OK) break;
+  }
+  restore();
+  return st;
+}
+}  // namespace
+
+extern "C" {
+
 fde_status fde_batch_solve(fde_batch* b, int concurrent, const double* const* yhat, const double* const* g,
                            double* const* y, double* const* u, double* const* zy, double* const* zu, double* const* p,
                            double* const* wy, double* const* wu, fde_admm_stats* stats, int32_t* status) {
@@ -1659,6 +1951,23 @@ fde_status fde_batch_solve(fde_batch* b, int concurrent, const double* const* yh
     return (fde_status)fail(FDE_EINVAL, "fde_batch_solve: null argument");
   const int n = (int)b->ctx.size();
   std::vector<fde_status> res(n, FDE_OK);
+  if (concurrent == 2) {
+    std::vector<AdmmRun> R(n);
+    const fde_status ls = batch_lockstep(b, yhat, g, y, u, zy, zu, p, wy, wu, R, res);
+    if (ls == FDE_OK) {
+      for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+      fde_status worst = FDE_OK;
+      for (int i = 0; i < n; ++i) {
+        if (stats) stats[i] = R[i].st;
+        if (status) status[i] = res[i];
+        if (res[i] < 0 && worst >= 0) worst = res[i];
+        if (res[i] == FDE_ENOTCONV && worst == FDE_OK) worst = FDE_ENOTCONV;
+      }
+      return worst;
+    }
+    if (ls != FDE_EINVAL) return ls;
+    concurrent = 1;  // no batched form for these instances: the concurrent mode
+  }
   if (!concurrent) {
     for (int i = 0; i < n; ++i) {
       fde_admm_stats st{};

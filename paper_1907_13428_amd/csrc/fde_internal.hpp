@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fde.h"
@@ -38,17 +40,6 @@ struct PassEventQueue {
   int n = 0, next = 0;
 };
 extern thread_local PassEventQueue t_pass_events;
-
-template <typename Arg>
-inline void launch_pass(void (*kern)(Arg), int blocks, int threads, hipStream_t s, const Arg& a) {
-  PassEventQueue& q = t_pass_events;
-  if (q.next < q.n) {
-    const int k = q.next++;
-    hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, q.ev[2 * k], q.ev[2 * k + 1], 0, a);
-  } else {
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, a);
-  }
-}
 
 // 16-byte accesses of two adjacent doubles (fields are 16-byte aligned and nx is even)
 __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
@@ -146,6 +137,64 @@ struct PrecondArgs {
   int pdir;             // x-inverse output into z: 0 the preconditioned residual; 1 p = z + beta p
                         // (z is the direction p, updated in place); 2 p = z (the first direction)
 };
+
+// ---------------------------------------------------------------------------
+// Batched passes.  A pass kernel launched with batch arguments works on many
+// independent instances at once: block b of the launch runs block
+// b - first[i] (of first[i+1] - first[i]) of instance i, the largest i with
+// first[i] <= b, with that instance's own arguments from the table args[i].
+// Every instance keeps the block decomposition of its own single launch, so
+// its results are bit for bit those of that launch.
+// ---------------------------------------------------------------------------
+template <typename Args> struct BatchArgs {
+  const Args* args;   // [count] per-instance arguments (device)
+  const int* first;   // [count + 1] first launch block of each instance (device)
+  int count;
+};
+
+template <typename Args>
+__device__ __forceinline__ int batch_instance(const BatchArgs<Args>& b, int blk) {
+  int lo = 0, hi = b.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.first[mid] <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// A recorded pass launch (the host records an instance's PCG iteration once,
+// then issues the passes of all instances as batched launches).
+struct RecordedPass {
+  const void* batch_kernel = nullptr;  // the BatchArgs twin of the kernel (null: no batched form)
+  int blocks = 0, threads = 0;
+  int kind = 0;                        // 0: LinePassArgs, 1: PrecondArgs
+  alignas(16) unsigned char args[512];
+};
+extern thread_local std::vector<RecordedPass>* t_record;
+
+template <typename Arg>
+inline void launch_pass(void (*kern)(Arg), void (*batch_kern)(BatchArgs<Arg>), int blocks, int threads,
+                        hipStream_t s, const Arg& a) {
+  if (t_record) {
+    static_assert(sizeof(Arg) <= sizeof(RecordedPass::args), "argument block");
+    RecordedPass r;
+    r.batch_kernel = reinterpret_cast<const void*>(batch_kern);
+    r.blocks = blocks;
+    r.threads = threads;
+    r.kind = std::is_same<Arg, LinePassArgs>::value ? 0 : 1;
+    std::memcpy(r.args, &a, sizeof(Arg));
+    t_record->push_back(r);
+    return;
+  }
+  PassEventQueue& q = t_pass_events;
+  if (q.next < q.n) {
+    const int k = q.next++;
+    hipExtLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, q.ev[2 * k], q.ev[2 * k + 1], 0, a);
+  } else {
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), 0, s, a);
+  }
+}
 
 // stage 0: all five passes; 1: the x-forward pass only; 2: passes 2-5; 11..15: pass 1..5 alone
 hipError_t launch_precond_stage(const PrecondArgs& a, bool fp32, int stage, hipStream_t s, int* nb_fwd,
@@ -301,6 +350,8 @@ hipError_t launch_adjoint_rhs(int64_t n, int plane, const double* wts, const dou
 // partial sums of 1/2 J1 (y - yhat)^2 + gamma/2 J1 u^2
 hipError_t launch_objective(int64_t n, int plane, const double* wts, double gamma, const double* y,
                             const double* yhat, const double* u, double* partial, hipStream_t s, int* nb);
+// out[i] = ints[i][kDone] for the count instances of a batch
+hipError_t launch_gather_done(const int* const* ints, int count, int* out, hipStream_t s);
 // gradient pieces: dyhat = -J1 (y - yhat), lam = psi p
 hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const double* y, const double* yhat,
                               const double* p, double psi, double* dyhat, double* lam, hipStream_t s);

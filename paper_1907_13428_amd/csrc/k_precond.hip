@@ -48,7 +48,7 @@ constexpr int pre_x_groups(int T) { return kPreThreads / T + (kPreThreads % T ? 
 // pass 1: x-direction real-to-complex
 // ---------------------------------------------------------------------------
 template <int L, typename TS, bool FUSE>
-__global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
+__device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
   using V = cplx<TS>;
   constexpr int E = default_E(L);
   constexpr int T = L / E;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   if (a.done && *a.done) return;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int nlines = a.ny * a.nt;
-  const int pair = blockIdx.x * LPB + g;
+  const int pair = bid * LPB + g;
   const int l0 = 2 * pair, l1 = 2 * pair + 1;
   const bool h0 = g < LPB && l0 < nlines, h1 = g < LPB && l1 < nlines;
   LineLds<V> buf{lds + g * lpad_size(L), 1};
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
       // alpha = (r, z) / (p, q), every block summing the partials in the same order
       const double pq = block_ordered_sum<kPreThreads>(a.pq_partial, a.pq_n);
       alpha = a.scal[rz_slot(a.ints[kIter])] / pq;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bid == 0 && threadIdx.x == 0) {
         a.scal_w[kPQ] = pq;
         a.scal_w[kAlpha] = alpha;
       }
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   }
   if constexpr (FUSE) {
     const double s = block_sum<kPreThreads>(rr);
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) a.partial[bid] = s;
   }
 
   line_fft<L, E, -1>(v, buf, t, tw);
@@ -158,6 +158,18 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
   }
 }
 
+template <int L, typename TS, bool FUSE>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
+  pre_xfwd_body<L, TS, FUSE>(a, blockIdx.x);
+}
+
+// the batched twin: many instances in one launch (BatchArgs)
+template <int L, typename TS, bool FUSE>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xfwd_b(BatchArgs<PrecondArgs> b) {
+  const int i = batch_instance(b, blockIdx.x);
+  pre_xfwd_body<L, TS, FUSE>(b.args[i], blockIdx.x - b.first[i]);
+}
+
 // ---------------------------------------------------------------------------
 // passes 2/4 (y) and 3 (t): complex lines across rows of a [rows][H] plane,
 // P columns per block staged through LDS
@@ -179,7 +191,7 @@ template <int L, int S = 0> struct CCfg {
 // division by s (S~^{-1}).  MODE 2: t-direction with the product by
 // 1 / conj(psi (lt - ly - lx)), the inverse of the transposed circulant.
 template <int L, typename TS, int MODE, int SIGN, int S>
-__global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
+__device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int nbk) {
   using V = cplx<TS>;
   using C = CCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
@@ -187,7 +199,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   if (a.done && *a.done) return;
   const int H = a.H;
   const int tiles = (H + P - 1) / P;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_tile(bid, nbk);
   const int outer = tile / tiles;  // MODE 0: time slice; MODE 1, 2: ky row
   const int k0 = (tile % tiles) * P;
   // element (line index i, column c) address in the spectrum
@@ -233,7 +245,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
       const double rr = block_ordered_sum<NT>(a.rr_partial, a.rr_n);
       const double bb = a.scal[kBB], tol2 = a.scal[kTol2];
       const int conv = (rr != rr) ? -1 : (rr <= tol2 * bb ? 1 : 0);
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (bid == 0 && threadIdx.x == 0) {
         const int it = a.ints[kIter] + 1;
         a.scal_w[kRR] = rr;
         a.ints[kIter] = it;
@@ -246,7 +258,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
     }
   }
   if constexpr (MODE == 0 && SIGN > 0) {
-    if (a.rzs_partial && blockIdx.x == 0) {
+    if (a.rzs_partial && bid == 0) {
       // (r, z) from the t-pass partials, and beta = (r, z) / (r, z) of the
       // previous iteration (or the first (r, z) alone) for the x-inverse pass
       const double rz = block_ordered_sum<NT>(a.rzs_partial, a.rzs_n);
@@ -307,7 +319,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
         const bool col = active && kx < H;
         const double w = (kx == 0 || 2 * kx == a.nx) ? 1.0 : 2.0;
         const double s = block_sum<NT>(col ? w * rz : 0.0);
-        if (threadIdx.x == 0) a.rzs_partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) a.rzs_partial[bid] = s;
       }
     }
     line_fft<L, E, +1>(v, buf, t, tw);
@@ -328,12 +340,24 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
   }
 }
 
+template <int L, typename TS, int MODE, int SIGN, int S>
+__global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
+  pre_cc_body<L, TS, MODE, SIGN, S>(a, blockIdx.x, gridDim.x);
+}
+
+// the batched twin
+template <int L, typename TS, int MODE, int SIGN, int S>
+__global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc_b(BatchArgs<PrecondArgs> b) {
+  const int i = batch_instance(b, blockIdx.x);
+  pre_cc_body<L, TS, MODE, SIGN, S>(b.args[i], blockIdx.x - b.first[i], b.first[i + 1] - b.first[i]);
+}
+
 // ---------------------------------------------------------------------------
 // pass 5: half spectrum -> real lines.  OUT 0: z; 1: z and partial sums of
 // (r, z); 2: the PCG direction p = z + beta p, in place in a.z
 // ---------------------------------------------------------------------------
 template <int L, typename TS, int OUT>
-__global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
+__device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
   constexpr bool DOT = OUT == 1, UPD = OUT == 2;
   using V = cplx<TS>;
   constexpr int E = default_E(L);
@@ -344,7 +368,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
   if (a.done && *a.done) return;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int nlines = a.ny * a.nt;
-  const int pair = blockIdx.x * LPB + g;
+  const int pair = bid * LPB + g;
   const int l0 = 2 * pair, l1 = 2 * pair + 1;
   const bool h0 = g < LPB && l0 < nlines, h1 = g < LPB && l1 < nlines;
   LineLds<V> buf{lds + g * lpad_size(L), 1};
@@ -404,13 +428,44 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
   }
   if constexpr (DOT) {
     const double s = block_sum<kPreThreads>(rz);
-    if (threadIdx.x == 0) a.partial2[blockIdx.x] = s;
+    if (threadIdx.x == 0) a.partial2[bid] = s;
   }
+}
+
+template <int L, typename TS, int OUT>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
+  pre_xinv_body<L, TS, OUT>(a, blockIdx.x);
+}
+
+// the batched twin
+template <int L, typename TS, int OUT>
+__global__ __launch_bounds__(kPreThreads) void k_pre_xinv_b(BatchArgs<PrecondArgs> b) {
+  const int i = batch_instance(b, blockIdx.x);
+  pre_xinv_body<L, TS, OUT>(b.args[i], blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
+// Lengths whose PCG passes have batched twins: the axis lengths of the batched
+// workload's grids (64 .. 512 nodes in space, 16 and 32 time levels)
+constexpr bool batch_dim(int n) {
+  return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
+}
+using PreBatchKernel = void (*)(BatchArgs<PrecondArgs>);
+template <int L, typename TS, bool FUSE> static PreBatchKernel xfwd_twin() {
+  if constexpr (batch_dim(L) && FUSE) return k_pre_xfwd_b<L, TS, FUSE>;
+  else return nullptr;
+}
+template <int L, typename TS, int OUT> static PreBatchKernel xinv_twin() {
+  if constexpr (batch_dim(L) && OUT == 2) return k_pre_xinv_b<L, TS, OUT>;
+  else return nullptr;
+}
+template <int L, typename TS, int MODE, int SIGN, int S> static PreBatchKernel cc_twin() {
+  if constexpr (batch_dim(L) && MODE != 2) return k_pre_cc_b<L, TS, MODE, SIGN, S>;
+  else return nullptr;
+}
+
 #define FDE_FOR_DIM_LENGTHS(X)                                                                          \
   X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(50) X(64) X(80) X(96) X(100) X(128) X(160) X(192) X(256) \
   X(384) X(512) X(768) X(1024)
@@ -422,12 +477,12 @@ static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) 
   const int blocks = (pairs + LPB - 1) / LPB;
   if (nb) *nb = blocks;
   if (fwd) {
-    if (a.q) launch_pass(k_pre_xfwd<L, TS, true>, blocks, kPreThreads, s, a);
-    else launch_pass(k_pre_xfwd<L, TS, false>, blocks, kPreThreads, s, a);
+    if (a.q) launch_pass(k_pre_xfwd<L, TS, true>, xfwd_twin<L, TS, true>(), blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xfwd<L, TS, false>, xfwd_twin<L, TS, false>(), blocks, kPreThreads, s, a);
   } else {
-    if (a.pdir == 1) launch_pass(k_pre_xinv<L, TS, 2>, blocks, kPreThreads, s, a);
-    else if (a.partial2) launch_pass(k_pre_xinv<L, TS, 1>, blocks, kPreThreads, s, a);
-    else launch_pass(k_pre_xinv<L, TS, 0>, blocks, kPreThreads, s, a);
+    if (a.pdir == 1) launch_pass(k_pre_xinv<L, TS, 2>, xinv_twin<L, TS, 2>(), blocks, kPreThreads, s, a);
+    else if (a.partial2) launch_pass(k_pre_xinv<L, TS, 1>, xinv_twin<L, TS, 1>(), blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xinv<L, TS, 0>, xinv_twin<L, TS, 0>(), blocks, kPreThreads, s, a);
   }
   return hipGetLastError();
 }
@@ -436,8 +491,8 @@ template <int L, typename TS, int S>
 static hipError_t pre_y_S(const PrecondArgs& a, int sign, hipStream_t s) {
   using C = CCfg<L, S>;
   const int blocks = ((a.H + C::P - 1) / C::P) * a.nt;
-  if (sign < 0) launch_pass(k_pre_cc<L, TS, 0, -1, S>, blocks, C::NT, s, a);
-  else launch_pass(k_pre_cc<L, TS, 0, +1, S>, blocks, C::NT, s, a);
+  if (sign < 0) launch_pass(k_pre_cc<L, TS, 0, -1, S>, cc_twin<L, TS, 0, -1, S>(), blocks, C::NT, s, a);
+  else launch_pass(k_pre_cc<L, TS, 0, +1, S>, cc_twin<L, TS, 0, +1, S>(), blocks, C::NT, s, a);
   return hipGetLastError();
 }
 
@@ -454,8 +509,8 @@ template <int L, typename TS, int S>
 static hipError_t pre_t_S(const PrecondArgs& a, hipStream_t s) {
   using C = CCfg<L, S>;
   const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
-  if (a.div_mode == 1) launch_pass(k_pre_cc<L, TS, 2, -1, S>, blocks, C::NT, s, a);
-  else launch_pass(k_pre_cc<L, TS, 1, -1, S>, blocks, C::NT, s, a);
+  if (a.div_mode == 1) launch_pass(k_pre_cc<L, TS, 2, -1, S>, cc_twin<L, TS, 2, -1, S>(), blocks, C::NT, s, a);
+  else launch_pass(k_pre_cc<L, TS, 1, -1, S>, cc_twin<L, TS, 1, -1, S>(), blocks, C::NT, s, a);
   return hipGetLastError();
 }
 

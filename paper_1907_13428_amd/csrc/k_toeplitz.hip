@@ -27,8 +27,8 @@ constexpr int kLineThreads = 256;
 // PAD: the embedding is longer than 2n (L >= 2n, the length n read at run
 // time): elements n..L/2-1 of the data half are zero and only the first n
 // results are kept.  Without PAD, n = L/2 is known at compile time.
-template <int L, bool VAR, bool TRANS, bool PAD = false>
-__global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
+template <int L, bool VAR, bool TRANS, bool PAD>
+__device__ __forceinline__ void xpass_body(const LinePassArgs& a, int bid) {
   constexpr int E = default_E(L);
   constexpr int T = L / E;
   static_assert(T <= kLineThreads, "line too long for one block");
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
 
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int nlines = a.ny * a.nt;
-  const int pair = blockIdx.x * LPB + g;
+  const int pair = bid * LPB + g;
   const int l0 = 2 * pair, l1 = 2 * pair + 1;
   const bool h0 = l0 < nlines, h1 = l1 < nlines;
   LineLds<double2> buf{lds + g * lpad_size(L), 1};
@@ -162,6 +162,18 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
   }
 }
 
+template <int L, bool VAR, bool TRANS, bool PAD = false>
+__global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
+  xpass_body<L, VAR, TRANS, PAD>(a, blockIdx.x);
+}
+
+// the batched twin: many instances in one launch (BatchArgs)
+template <int L, bool VAR, bool TRANS, bool PAD = false>
+__global__ __launch_bounds__(kLineThreads) void k_xpass_b(BatchArgs<LinePassArgs> b) {
+  const int i = batch_instance(b, blockIdx.x);
+  xpass_body<L, VAR, TRANS, PAD>(b.args[i], blockIdx.x - b.first[i]);
+}
+
 // ---------------------------------------------------------------------------
 // y-pass: a block owns one time slice and 2P adjacent x-columns; the tile is
 // staged through LDS so that every global access is row-contiguous
@@ -186,8 +198,8 @@ template <int L, int S = 0> struct YCfg {
 // inverse transform of ((l_0 + l_1)/2) Z[k] + ((l_0 - l_1)/2) conj Z[L-k]
 // (Hermitian separation), so a pair costs two transforms instead of three.
 // PAD: as for the x-pass, an embedding longer than 2n (n = ny read at run time).
-template <int L, bool VAR, bool TRANS, int S, bool COL = false, bool PAD = false>
-__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
+template <int L, bool VAR, bool TRANS, int S, bool COL, bool PAD>
+__device__ __forceinline__ void ypass_body(const LinePassArgs& a, int bid, int nbk) {
   static_assert(!(VAR && COL), "per-column coefficients use the constant-coefficient tile path");
   using C = YCfg<L, S>;
   constexpr int E = C::E, T = C::T, P = C::P, NT = C::NT, RS = C::RS;
@@ -199,7 +211,7 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 
   const int nx = a.nx;
   const int tiles = (nx + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_tile(bid, nbk);
   const int slice = tile / tiles;
   const int x0 = (tile % tiles) * TX;
   const size_t sbase = (size_t)slice * n * nx;
@@ -376,8 +388,20 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   }
   if (a.dotv) {
     const double s = block_sum<NT>(dot);
-    if (tid == 0) a.partial[blockIdx.x] = s;
+    if (tid == 0) a.partial[bid] = s;
   }
+}
+
+template <int L, bool VAR, bool TRANS, int S, bool COL = false, bool PAD = false>
+__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
+  ypass_body<L, VAR, TRANS, S, COL, PAD>(a, blockIdx.x, gridDim.x);
+}
+
+// the batched twin
+template <int L, bool VAR, bool TRANS, int S, bool COL = false, bool PAD = false>
+__global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass_b(BatchArgs<LinePassArgs> b) {
+  const int i = batch_instance(b, blockIdx.x);
+  ypass_body<L, VAR, TRANS, S, COL, PAD>(b.args[i], blockIdx.x - b.first[i], b.first[i + 1] - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,14 +411,33 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 
+// Lengths whose constant-coefficient passes have batched twins: the FFT
+// lengths of the batched workload's grids (64 .. 512 nodes per axis)
+constexpr bool batch_embed(int L) {
+  return L == 128 || L == 192 || L == 256 || L == 384 || L == 512 || L == 768 || L == 1024;
+}
+using LineBatchKernel = void (*)(BatchArgs<LinePassArgs>);
+
+template <int L, bool VAR, bool TRANS, bool PAD>
+static LineBatchKernel xpass_twin() {
+  if constexpr (batch_embed(L) && !VAR && !PAD) return k_xpass_b<L, VAR, TRANS, PAD>;
+  else return nullptr;
+}
+
+template <int L, bool VAR, bool TRANS, int S, bool COL, bool PAD>
+static LineBatchKernel ypass_twin() {
+  if constexpr (batch_embed(L) && !VAR && !COL && !PAD) return k_ypass_b<L, VAR, TRANS, S, COL, PAD>;
+  else return nullptr;
+}
+
 template <int L, bool PAD>
 static void xpass_launch(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int blocks) {
   if (var) {
-    if (tr) launch_pass(k_xpass<L, true, true, PAD>, blocks, kLineThreads, s, a);
-    else launch_pass(k_xpass<L, true, false, PAD>, blocks, kLineThreads, s, a);
+    if (tr) launch_pass(k_xpass<L, true, true, PAD>, xpass_twin<L, true, true, PAD>(), blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, true, false, PAD>, xpass_twin<L, true, false, PAD>(), blocks, kLineThreads, s, a);
   } else {
-    if (tr) launch_pass(k_xpass<L, false, true, PAD>, blocks, kLineThreads, s, a);
-    else launch_pass(k_xpass<L, false, false, PAD>, blocks, kLineThreads, s, a);
+    if (tr) launch_pass(k_xpass<L, false, true, PAD>, xpass_twin<L, false, true, PAD>(), blocks, kLineThreads, s, a);
+    else launch_pass(k_xpass<L, false, false, PAD>, xpass_twin<L, false, false, PAD>(), blocks, kLineThreads, s, a);
   }
 }
 
@@ -423,14 +466,20 @@ template <int L, int S, bool PAD>
 static void ypass_launch(const LinePassArgs& a, bool tr, bool var, hipStream_t s, int blocks) {
   using C = YCfg<L, S>;
   if (a.col_coef) {
-    if (tr) launch_pass(k_ypass<L, false, true, S, true, PAD>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, false, false, S, true, PAD>, blocks, C::NT, s, a);
+    if (tr) launch_pass(k_ypass<L, false, true, S, true, PAD>, ypass_twin<L, false, true, S, true, PAD>(), blocks,
+                        C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S, true, PAD>, ypass_twin<L, false, false, S, true, PAD>(), blocks,
+                     C::NT, s, a);
   } else if (var) {
-    if (tr) launch_pass(k_ypass<L, true, true, S, false, PAD>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, true, false, S, false, PAD>, blocks, C::NT, s, a);
+    if (tr) launch_pass(k_ypass<L, true, true, S, false, PAD>, ypass_twin<L, true, true, S, false, PAD>(), blocks,
+                        C::NT, s, a);
+    else launch_pass(k_ypass<L, true, false, S, false, PAD>, ypass_twin<L, true, false, S, false, PAD>(), blocks,
+                     C::NT, s, a);
   } else {
-    if (tr) launch_pass(k_ypass<L, false, true, S, false, PAD>, blocks, C::NT, s, a);
-    else launch_pass(k_ypass<L, false, false, S, false, PAD>, blocks, C::NT, s, a);
+    if (tr) launch_pass(k_ypass<L, false, true, S, false, PAD>, ypass_twin<L, false, true, S, false, PAD>(), blocks,
+                        C::NT, s, a);
+    else launch_pass(k_ypass<L, false, false, S, false, PAD>, ypass_twin<L, false, false, S, false, PAD>(), blocks,
+                     C::NT, s, a);
   }
 }
 

@@ -429,4 +429,14 @@ hipError_t launch_grad_fields(int64_t n, int plane, const double* wts, const dou
   return hipGetLastError();
 }
 
+// the PCG done flags of many instances gathered into one array (one readback)
+__global__ __launch_bounds__(kBlock) void k_gather_done(const int* const* ints, int count, int* out) {
+  for (int i = threadIdx.x; i < count; i += kBlock) out[i] = ints[i][kDone];
+}
+
+hipError_t launch_gather_done(const int* const* ints, int count, int* out, hipStream_t s) {
+  k_gather_done<<<1, kBlock, 0, s>>>(ints, count, out);
+  return hipGetLastError();
+}
+
 }  // namespace fde

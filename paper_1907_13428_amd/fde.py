@@ -360,8 +360,10 @@ class Batch:
     def __exit__(self, *exc):
         self.close()
 
-    def solve(self, yhats, states=None, concurrent=True):
-        """Solve every instance; returns (states, list of stats dicts, list of statuses)."""
+    def solve(self, yhats, states=None, concurrent=True, lockstep=False):
+        """Solve every instance; returns (states, list of stats dicts, list of statuses).
+        lockstep: all instances in step, their Krylov iterations as batched pass
+        launches (falls back to the concurrent mode where that is unavailable)."""
         import torch
 
         n = self.count
@@ -374,5 +376,6 @@ class Batch:
         cols = [arr([states[i][k] for i in range(n)]) for k in self.FIELDS]
         st = (Stats * n)()
         code = (ctypes.c_int32 * n)()
-        _check(lib().fde_batch_solve(self._h, int(bool(concurrent)), yh, None, *cols, st, code))
+        mode = 2 if lockstep else int(bool(concurrent))
+        _check(lib().fde_batch_solve(self._h, mode, yh, None, *cols, st, code))
         return states, [s.as_dict() for s in st], list(code)

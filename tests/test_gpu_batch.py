@@ -94,3 +94,99 @@ def test_batch_mixed_methods_concurrent_equals_sequential_and_oracle():
         assert abs(sa[i]["pcg_total"] - sum(ref.pcg_iters)) <= 20, (i, sa[i]["pcg_total"], sum(ref.pcg_iters))
         for k in ("y", "u", "p", "wy", "wu"):
             assert rel(a[i][k], getattr(ref, k)) <= 1e-7, (i, k)
+
+
+def batchable(count=4, seed=21, maxit=None):
+    """Uneven instances on lengths with batched passes (64, 96, 128 nodes in
+    space; 16 and 32 time levels)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(count):
+        nx, ny = int(rng.choice([64, 96, 128])), int(rng.choice([64, 96, 128]))
+        nt = int(rng.choice([16, 32]))
+        w = W.small_mixed(nx=nx, ny=ny, nt=nt).replace(alpha=float(rng.uniform(1.1, 1.9)),
+                                                       beta=float(rng.uniform(1.1, 1.9)),
+                                                       gamma=float(10 ** rng.uniform(-5, -3)))
+        w.yhat = W.target_grf(nx, ny, nt, W.BASE_SEED + 200 + i)
+        if maxit is not None:
+            w = w.replace(admm_tol=0.0, admm_maxit=maxit + 3 * i)
+        out.append(w)
+    return out
+
+
+def run_mode(ws, mode, fp32=0):
+    probs, prms = zip(*[fde.from_workload(w, precond_fp32=fp32) for w in ws])
+    with fde.Batch(list(probs), list(prms)) as b:
+        states, stats, codes = b.solve([dev(w.yhat) for w in ws], concurrent=(mode != "sequential"),
+                                       lockstep=(mode == "lockstep"))
+        return [{k: host(v) for k, v in s.items()} for s in states], stats, codes
+
+
+def max_rel(a, b):
+    nb = float(np.max(np.abs(b)))
+    return float(np.max(np.abs(a - b))) / (nb if nb > 0 else 1.0)
+
+
+# The batched pass kernels run the single kernels' code on arguments read from
+# a table; the compiler may round a few operations differently there (measured
+# in FP64: a few ulps, <= 1.4e-15 relative after six ADMM iterations), so the
+# lockstep run is compared with the per-instance solves to 1e-12, with equal
+# counts.  With the FP32 preconditioner the same few-ulp differences are float
+# ulps inside the preconditioner, which the FP64 PCG absorbs to its tolerance:
+# the bar is that of the PCG parity cases, 1e-9.
+LOCKSTEP_BAR = 1e-12
+LOCKSTEP_BAR_FP32 = 1e-9
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_batch_lockstep_equals_sequential_and_oracle(fp32):
+    """Lockstep mode (the Krylov iterations of all instances as batched pass
+    launches): uneven instances with different ADMM budgets take the same
+    Krylov and ADMM iteration counts as the per-instance solves and the same
+    iterates to rounding, and follow the oracle."""
+    banner("batch lockstep vs sequential", fp32)
+    ws = batchable(maxit=6)
+    a, sa, ca = run_mode(ws, "lockstep", fp32)
+    b, sb, cb = run_mode(ws, "sequential", fp32)
+    assert ca == cb
+    for i in range(len(ws)):
+        assert sa[i]["admm_iters"] == sb[i]["admm_iters"] == ws[i].admm_maxit
+        assert sa[i]["pcg_total"] == sb[i]["pcg_total"]
+        bar = LOCKSTEP_BAR_FP32 if fp32 else LOCKSTEP_BAR
+        for k in a[i]:
+            assert max_rel(a[i][k], b[i][k]) <= bar, (i, k, max_rel(a[i][k], b[i][k]))
+    for i in (0, 3):
+        ref = admm.admm_solve(ws[i], iters=ws[i].admm_maxit)
+        for k in ("y", "u", "p"):
+            assert rel(a[i][k], getattr(ref, k)) <= 1e-7, (i, k)
+
+
+def test_batch_lockstep_converging_instances():
+    """Instances that stop at different ADMM iterations on the stopping test:
+    the lockstep run keeps the finished ones out and equals the per-instance
+    solves."""
+    banner("batch lockstep converging")
+    # the paper's test problem on 64^3 with implicit Euler in time, three box settings
+    ws = [W.paper_test(64, alpha_t=1.0, ya=ya, ua=ua, delta=0.4).replace(admm_maxit=400)
+          for ya, ua in ((-7.0, -400.0), (-4.0, -350.0), (-1.0, -400.0))]
+    a, sa, ca = run_mode(ws, "lockstep")
+    b, sb, cb = run_mode(ws, "sequential")
+    assert ca == cb
+    assert len({s["admm_iters"] for s in sb}) > 1  # the instances stop at different iterations
+    for i in range(len(ws)):
+        assert sa[i]["admm_iters"] == sb[i]["admm_iters"]
+        for k in a[i]:
+            assert max_rel(a[i][k], b[i][k]) <= LOCKSTEP_BAR, (i, k)
+
+
+def test_batch_lockstep_falls_back_without_batched_passes():
+    """Lengths without batched passes (and the MINRES x-step) make the lockstep
+    request run the concurrent mode: same results as sequential."""
+    banner("batch lockstep fallback")
+    ws = uneven(count=3, seed=2)
+    ws = [w.replace(admm_tol=0.0, admm_maxit=8) for w in ws]
+    a, sa, _ = run_mode(ws, "lockstep")
+    b, sb, _ = run_mode(ws, "sequential")
+    for i in range(len(ws)):
+        for k in a[i]:
+            assert np.array_equal(a[i][k], b[i][k]), (i, k)
