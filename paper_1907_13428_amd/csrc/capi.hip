@@ -10,6 +10,7 @@
 
 #include <array>
 #include <chrono>
+#include <climits>
 #include <thread>
 #include <cmath>
 #include <cstdio>
@@ -1629,22 +1630,32 @@ void batch_free(fde_batch* b) {
 struct PassGroup {
   const void* kern = nullptr;
   int threads = 0, blocks = 0, count = 0;
-  const void* args = nullptr;  // device table of the instances' arguments
+  const void* args = nullptr;  // device table of the members' arguments
   const int* first = nullptr;  // device prefix sums of their block counts
 };
 
-struct BatchPcg {
+// The launches of one batch iteration over a set of members, and the device
+// tables they read (one region: argument and prefix tables per group, the
+// members' int-slot pointers, their gathered done flags).
+struct BatchPlan {
   std::vector<std::vector<PassGroup>> pos;  // per pass position, its kernel groups
-  void* dev = nullptr;                      // one allocation: tables, ints pointers, flags
+  std::vector<int> members;                 // instance indices
   const int* const* ints = nullptr;
   int* flags = nullptr;
-  int* h_flags = nullptr;  // pinned
+};
+
+struct BatchPcg {
+  std::vector<std::vector<fde::RecordedPass>> rec;  // per instance, its recorded PCG iteration
+  size_t region = 0;               // bytes of one plan region
+  void* dev = nullptr;             // region 0: the full plan (graph); region 1: subset plans
+  unsigned char* stage = nullptr;  // pinned staging of region 1
+  int* h_flags = nullptr;          // pinned
   hipEvent_t ev = nullptr;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  BatchPlan full, sub;
   int count = 0;
-  int launches = 0;  // pass launches per batch iteration
 };
 
 void batch_pcg_free(BatchPcg* bp) {
@@ -1653,12 +1664,13 @@ void batch_pcg_free(BatchPcg* bp) {
   if (bp->cap) (void)hipStreamDestroy(bp->cap);
   if (bp->ev) (void)hipEventDestroy(bp->ev);
   if (bp->h_flags) (void)hipHostFree(bp->h_flags);
+  if (bp->stage) (void)hipHostFree(bp->stage);
   if (bp->dev) (void)hipFree(bp->dev);
   *bp = BatchPcg{};
 }
 
-hipError_t batch_pcg_iteration(const BatchPcg* bp, hipStream_t s) {
-  for (const auto& groups : bp->pos)
+hipError_t batch_pcg_iteration(const BatchPlan& pl, hipStream_t s) {
+  for (const auto& groups : pl.pos)
     for (const PassGroup& g : groups) {
       fde::BatchArgs<fde::LinePassArgs> ba{static_cast<const fde::LinePassArgs*>(g.args), g.first, g.count};
       void* kargs[] = {&ba};
@@ -1668,37 +1680,25 @@ hipError_t batch_pcg_iteration(const BatchPcg* bp, hipStream_t s) {
   return hipSuccess;
 }
 
-// Record and group the PCG iterations of the instances cs (solution fields xs);
-// FDE_EINVAL when a pass has no batched form (the caller runs another mode).
-fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<double*>& xs, BatchPcg* bp) {
+// Group the recorded passes of `members` by kernel at each position and lay
+// out their tables in `host` (region bytes, zeroed by the caller), with device
+// addresses relative to `base`.  Returns the bytes used, 0 when they exceed
+// `cap` (never for a subset of the members the region was sized for).
+size_t batch_plan(const BatchPcg& bp, const std::vector<fde_ctx*>& cs, const std::vector<int>& members,
+                  unsigned char* host, unsigned char* base, size_t cap, BatchPlan* pl) {
   using fde::RecordedPass;
-  const int n = (int)cs.size();
-  std::vector<std::vector<RecordedPass>> rec(n);
-  for (int i = 0; i < n; ++i) {
-    fde::t_record = &rec[i];
-    const hipError_t e = enqueue_pcg_iteration_passes(cs[i], xs[i]);
-    fde::t_record = nullptr;
-    if (e != hipSuccess) return (fde_status)fail(FDE_EHIP, std::string("batch record: ") + hipGetErrorString(e));
-  }
-  const size_t npos = rec[0].size();
-  for (int i = 0; i < n; ++i) {
-    if (rec[i].size() != npos) return (fde_status)fail(FDE_EINVAL, "batch: instances with different pass lists");
-    for (const RecordedPass& r : rec[i])
-      if (!r.batch_kernel) return (fde_status)fail(FDE_EINVAL, "batch: a pass without a batched form");
-  }
-  // layout of the device buffer: per group, its argument table and prefix table
+  const size_t npos = bp.rec[members[0]].size();
   struct GroupHost {
     size_t pos;
     const void* kern;
     int threads, kind;
     std::vector<int> members;
-    size_t slot = 0;  // index among its position's groups
   };
   std::vector<GroupHost> groups;
   for (size_t p = 0; p < npos; ++p) {
     const size_t g0 = groups.size();
-    for (int i = 0; i < n; ++i) {
-      const RecordedPass& r = rec[i][p];
+    for (int i : members) {
+      const RecordedPass& r = bp.rec[i][p];
       size_t g = g0;
       while (g < groups.size() && groups[g].kern != r.batch_kernel) ++g;
       if (g == groups.size()) groups.push_back(GroupHost{p, r.batch_kernel, r.threads, r.kind, {}});
@@ -1706,6 +1706,7 @@ fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<do
     }
   }
   auto align = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t m = members.size();
   size_t total = 0;
   std::vector<size_t> off_args(groups.size()), off_first(groups.size());
   for (size_t g = 0; g < groups.size(); ++g) {
@@ -1716,21 +1717,22 @@ fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<do
     total = align(total + sizeof(int) * (groups[g].members.size() + 1));
   }
   const size_t off_ints = total;
-  total = align(total + sizeof(int*) * n);
+  total = align(total + sizeof(int*) * m);
   const size_t off_flags = total;
-  total = align(total + sizeof(int) * n);
-  std::vector<unsigned char> host(total, 0);
-  bp->pos.assign(npos, {});
-  int launches = 0;
+  total = align(total + sizeof(int) * m);
+  if (!host) return total;  // sizing pass
+  if (total > cap) return 0;
+  pl->pos.assign(npos, {});
+  pl->members = members;
   for (size_t g = 0; g < groups.size(); ++g) {
     const GroupHost& G = groups[g];
     const size_t asz = G.kind == 0 ? sizeof(fde::LinePassArgs) : sizeof(fde::PrecondArgs);
-    int* first = reinterpret_cast<int*>(host.data() + off_first[g]);
+    int* first = reinterpret_cast<int*>(host + off_first[g]);
     int blocks = 0;
-    for (size_t m = 0; m < G.members.size(); ++m) {
-      const RecordedPass& r = rec[G.members[m]][G.pos];
-      std::memcpy(host.data() + off_args[g] + asz * m, r.args, asz);
-      first[m] = blocks;
+    for (size_t k = 0; k < G.members.size(); ++k) {
+      const RecordedPass& r = bp.rec[G.members[k]][G.pos];
+      std::memcpy(host + off_args[g] + asz * k, r.args, asz);
+      first[k] = blocks;
       blocks += r.blocks;
     }
     first[G.members.size()] = blocks;
@@ -1739,31 +1741,52 @@ fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<do
     pg.threads = G.threads;
     pg.blocks = blocks;
     pg.count = (int)G.members.size();
-    groups[g].slot = bp->pos[G.pos].size();
-    bp->pos[G.pos].push_back(pg);
-    ++launches;
+    pg.args = base + off_args[g];
+    pg.first = reinterpret_cast<const int*>(base + off_first[g]);
+    pl->pos[G.pos].push_back(pg);
   }
-  const int** ints_host = reinterpret_cast<const int**>(host.data() + off_ints);
-  for (int i = 0; i < n; ++i) ints_host[i] = cs[i]->ints;
-  HIP_TRY(hipMalloc(&bp->dev, total));
-  HIP_TRY(hipMemcpy(bp->dev, host.data(), total, hipMemcpyHostToDevice));
+  const int** ints_host = reinterpret_cast<const int**>(host + off_ints);
+  for (size_t k = 0; k < m; ++k) ints_host[k] = cs[members[k]]->ints;
+  pl->ints = reinterpret_cast<const int* const*>(base + off_ints);
+  pl->flags = reinterpret_cast<int*>(base + off_flags);
+  return total;
+}
+
+// Record the PCG iterations of the instances cs (solution fields xs), build the
+// plan over all of them and capture kGraphIters of its iterations in a graph;
+// FDE_EINVAL when a pass has no batched form (the caller runs another mode).
+fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<double*>& xs, BatchPcg* bp) {
+  using fde::RecordedPass;
+  const int n = (int)cs.size();
+  bp->rec.assign(n, {});
+  for (int i = 0; i < n; ++i) {
+    fde::t_record = &bp->rec[i];
+    const hipError_t e = enqueue_pcg_iteration_passes(cs[i], xs[i]);
+    fde::t_record = nullptr;
+    if (e != hipSuccess) return (fde_status)fail(FDE_EHIP, std::string("batch record: ") + hipGetErrorString(e));
+  }
+  const size_t npos = bp->rec[0].size();
+  for (int i = 0; i < n; ++i) {
+    if (bp->rec[i].size() != npos) return (fde_status)fail(FDE_EINVAL, "batch: instances with different pass lists");
+    for (const RecordedPass& r : bp->rec[i])
+      if (!r.batch_kernel) return (fde_status)fail(FDE_EINVAL, "batch: a pass without a batched form");
+  }
+  std::vector<int> all(n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  bp->region = batch_plan(*bp, cs, all, nullptr, nullptr, 0, nullptr);
+  HIP_TRY(hipMalloc(&bp->dev, 2 * bp->region));
+  HIP_TRY(hipHostMalloc((void**)&bp->stage, bp->region, hipHostMallocDefault));
+  std::vector<unsigned char> host(bp->region, 0);
   unsigned char* d = static_cast<unsigned char*>(bp->dev);
-  for (size_t g = 0; g < groups.size(); ++g) {
-    PassGroup& pg = bp->pos[groups[g].pos][groups[g].slot];
-    pg.args = d + off_args[g];
-    pg.first = reinterpret_cast<const int*>(d + off_first[g]);
-  }
-  bp->ints = reinterpret_cast<const int* const*>(d + off_ints);
-  bp->flags = reinterpret_cast<int*>(d + off_flags);
+  (void)batch_plan(*bp, cs, all, host.data(), d, bp->region, &bp->full);
+  HIP_TRY(hipMemcpy(bp->dev, host.data(), bp->region, hipMemcpyHostToDevice));
   bp->count = n;
-  bp->launches = launches;
   HIP_TRY(hipHostMalloc((void**)&bp->h_flags, sizeof(int) * n, hipHostMallocDefault));
   HIP_TRY(hipEventCreateWithFlags(&bp->ev, hipEventDisableTiming));
-  // kGraphIters batch iterations captured once
   HIP_TRY(hipStreamCreateWithFlags(&bp->cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(bp->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int k = 0; k < kGraphIters && e == hipSuccess; ++k) e = batch_pcg_iteration(bp, bp->cap);
+  for (int k = 0; k < kGraphIters && e == hipSuccess; ++k) e = batch_pcg_iteration(bp->full, bp->cap);
   const hipError_t e2 = hipStreamEndCapture(bp->cap, &bp->graph);
   if (e != hipSuccess || e2 != hipSuccess)
     return (fde_status)fail(FDE_EHIP, std::string("batch graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
@@ -1771,25 +1794,30 @@ fde_status batch_pcg_build(const std::vector<fde_ctx*>& cs, const std::vector<do
   return FDE_OK;
 }
 
-// Batch iterations until every instance's PCG done flag is set (first chunk:
-// `predict` iterations rounded up to whole graphs; then one graph at a time).
-fde_status batch_pcg_run(BatchPcg* bp, hipStream_t s, int predict, int maxit) {
-  int chunk = ((std::max(predict, 1) + kGraphIters - 1) / kGraphIters) * kGraphIters;
-  int enqueued = 0;
-  while (true) {
-    for (int k = 0; k < chunk; k += kGraphIters) HIP_TRY(hipGraphLaunch(bp->exec, s));
-    enqueued += chunk;
-    HIP_TRY(fde::launch_gather_done(bp->ints, bp->count, bp->flags, s));
-    HIP_TRY(hipMemcpyAsync(bp->h_flags, bp->flags, sizeof(int) * bp->count, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(bp->ev, s));
-    HIP_TRY(hipEventSynchronize(bp->ev));
-    bool all = true;
-    for (int i = 0; i < bp->count; ++i) all = all && bp->h_flags[i] != 0;
-    if (all) return FDE_OK;
-    // every instance stops by its own iteration limit; this is a guard only
-    if (enqueued > maxit + kGraphIters) return (fde_status)fail(FDE_EHIP, "batched PCG: done flags not set");
-    chunk = kGraphIters;
+// Plan over a subset of the instances in region 1, uploaded on stream s (the
+// previous subset plan's launches on s have finished: the caller waited).
+fde_status batch_subset(BatchPcg* bp, const std::vector<fde_ctx*>& cs, const std::vector<int>& members, hipStream_t s) {
+  std::memset(bp->stage, 0, bp->region);
+  unsigned char* d1 = static_cast<unsigned char*>(bp->dev) + bp->region;
+  const size_t used = batch_plan(*bp, cs, members, bp->stage, d1, bp->region, &bp->sub);
+  if (used == 0) return (fde_status)fail(FDE_EHIP, "batch: subset tables exceed the region");
+  HIP_TRY(hipMemcpyAsync(d1, bp->stage, used, hipMemcpyHostToDevice, s));
+  return FDE_OK;
+}
+
+// Enqueue `iters` batch iterations of plan pl (the full plan as whole graphs),
+// then gather its members' done flags into pinned memory behind bp->ev.
+fde_status batch_chunk(BatchPcg* bp, const BatchPlan& pl, bool full, int iters, hipStream_t s) {
+  if (full) {
+    for (int k = 0; k < iters; k += kGraphIters) HIP_TRY(hipGraphLaunch(bp->exec, s));
+  } else {
+    for (int k = 0; k < iters; ++k) HIP_TRY(batch_pcg_iteration(pl, s));
   }
+  const int m = (int)pl.members.size();
+  HIP_TRY(fde::launch_gather_done(pl.ints, m, pl.flags, s));
+  HIP_TRY(hipMemcpyAsync(bp->h_flags, pl.flags, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipEventRecord(bp->ev, s));
+  return FDE_OK;
 }
 }  // namespace
 
@@ -1841,12 +1869,17 @@ fde_status fde_batch_destroy(fde_batch* b) {
 }  // extern "C"
 
 namespace {
-// Lockstep mode of fde_batch_solve: every instance on one stream, phase by
-// phase; the Krylov iterations of all instances in a PCG phase as batched
-// pass launches (a graph of kGraphIters batch iterations), the other phases
-// as each instance's own launches.  FDE_EINVAL (nothing run) when an instance
-// has no batched form (MINRES x-step, a fractional time order, lengths
-// without batched twins): the caller then runs the concurrent mode.
+// Lockstep mode of fde_batch_solve.  Each instance runs its ADMM phases on its
+// own stream; the Krylov iterations of the x-steps run as batched pass
+// launches on one more stream.  A batch starts when every live instance has
+// enqueued its x-step set-up (the instances' ADMM iterations stay in step);
+// its first chunk covers the largest iteration count of the previous x-steps.
+// After each chunk the converged instances leave the launch plan (their blocks
+// would only return at once) and go on with their update phases on their own
+// streams while the others continue in the batch.  FDE_EINVAL (nothing run)
+// when an instance has no batched form (MINRES x-step, a fractional time
+// order, lengths without batched twins): the caller then runs the concurrent
+// mode.
 fde_status batch_lockstep(fde_batch* b, const double* const* yhat, const double* const* g, double* const* y,
                           double* const* u, double* const* zy, double* const* zu, double* const* p,
                           double* const* wy, double* const* wu, std::vector<AdmmRun>& R,
@@ -1857,38 +1890,38 @@ fde_status batch_lockstep(fde_batch* b, const double* const* yhat, const double*
       return (fde_status)fail(FDE_EINVAL, "lockstep batch: an instance without batched passes");
   if (!b->lockstep) HIP_TRY(hipStreamCreateWithFlags(&b->lockstep, hipStreamNonBlocking));
   hipStream_t ls = b->lockstep;
-  std::vector<hipStream_t> saved(n);
   for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(b->ctx[i]->stream));
-  for (int i = 0; i < n; ++i) {
-    saved[i] = b->ctx[i]->stream;
-    b->ctx[i]->stream = ls;
-  }
+  const std::vector<fde_ctx*>& cs = b->ctx;
+  const std::vector<double*> xs(y, y + n);
   BatchPcg bp;
-  std::vector<fde_ctx*> cs;
-  std::vector<double*> xs;
-  for (int i = 0; i < n; ++i) {
-    cs.push_back(b->ctx[i]);
-    xs.push_back(y[i]);
-  }
-  fde_status st = batch_pcg_build(cs, xs, &bp);
-  auto restore = [&]() {
+  std::vector<hipEvent_t> join(n, nullptr);
+  auto cleanup = [&]() {
     (void)hipStreamSynchronize(ls);
-    for (int i = 0; i < n; ++i) b->ctx[i]->stream = saved[i];
+    for (fde_ctx* c : cs) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
     batch_pcg_free(&bp);
   };
+  fde_status st = batch_pcg_build(cs, xs, &bp);
+  for (int i = 0; i < n && st == FDE_OK; ++i) {
+    const hipError_t e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+    if (e != hipSuccess) st = (fde_status)fail(FDE_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+  }
   if (st != FDE_OK) {
-    restore();
+    cleanup();
     return st;
   }
-  std::vector<char> live(n, 0);
+  enum : char { LS_WAIT, LS_BATCH, LS_RUN };  // set-up enqueued / in the batch / own-stream phase pending
+  std::vector<char> live(n, 0), state(n, LS_RUN);
   int remaining = 0, maxit = 0;
   for (int i = 0; i < n; ++i) {
-    res[i] = admm_begin(b->ctx[i], &R[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i],
+    res[i] = admm_begin(cs[i], &R[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i],
                         true);
-    maxit = std::max(maxit, b->ctx[i]->prm.krylov_maxit);
+    maxit = std::max(maxit, cs[i]->prm.krylov_maxit);
     if (res[i] >= 0) {
       live[i] = 1;
       ++remaining;
+      state[i] = R[i].phase == PH_PCG ? LS_WAIT : LS_RUN;
     }
   }
   auto drop = [&](int i, fde_status s2) {
@@ -1896,48 +1929,88 @@ fde_status batch_lockstep(fde_batch* b, const double* const* yhat, const double*
     live[i] = 0;
     --remaining;
   };
-  while (remaining > 0) {
-    // Krylov phase of every instance that is in one, as batched iterations
-    int predict = 0;
-    bool any_pcg = false;
-    for (int i = 0; i < n; ++i)
-      if (live[i] && R[i].phase == PH_PCG) {
-        any_pcg = true;
-        predict = std::max(predict, R[i].predict);
+  // Iterations of the next chunk: up to the first predicted convergence among
+  // the members (each x-step usually needs about as many iterations as the
+  // previous one), so that finished instances leave the plan soon after.
+  auto next_chunk = [&](const std::vector<int>& members, int done_iters) {
+    int lo = INT_MAX;
+    for (int i : members) lo = std::min(lo, R[i].predict - done_iters);
+    return std::max(kGraphIters, ((lo + kGraphIters - 1) / kGraphIters) * kGraphIters);
+  };
+  bool in_flight = false, full = false;
+  int enqueued = 0;
+  while (remaining > 0 && st == FDE_OK) {
+    bool progress = false;
+    if (!in_flight) {
+      std::vector<int> members;
+      bool all_wait = true;
+      for (int i = 0; i < n; ++i) {
+        if (!live[i]) continue;
+        if (state[i] == LS_WAIT) members.push_back(i);
+        else all_wait = false;
       }
-    if (any_pcg) {
-      st = batch_pcg_run(&bp, ls, predict, maxit);
-      if (st != FDE_OK) break;
-      for (int i = 0; i < n; ++i)
-        if (live[i] && R[i].phase == PH_PCG) {
-          const fde_status s2 = post_readback(b->ctx[i]);
+      if (all_wait && !members.empty()) {
+        for (int i : members) {
+          hipError_t e = hipEventRecord(join[i], cs[i]->stream);
+          if (e == hipSuccess) e = hipStreamWaitEvent(ls, join[i], 0);
+          if (e != hipSuccess) st = (fde_status)fail(FDE_EHIP, std::string("lockstep join: ") + hipGetErrorString(e));
+          state[i] = LS_BATCH;
+        }
+        full = (int)members.size() == n;
+        if (!full && st == FDE_OK) st = batch_subset(&bp, cs, members, ls);
+        enqueued = 0;
+        const int chunk = next_chunk(members, 0);
+        if (st == FDE_OK) st = batch_chunk(&bp, full ? bp.full : bp.sub, full, chunk, ls);
+        enqueued = chunk;
+        in_flight = true;
+        progress = true;
+      }
+    } else {
+      const hipError_t q = hipEventQuery(bp.ev);
+      if (q == hipSuccess) {
+        progress = true;
+        const BatchPlan& pl = full ? bp.full : bp.sub;
+        std::vector<int> done, still;
+        for (size_t k = 0; k < pl.members.size(); ++k) (bp.h_flags[k] ? done : still).push_back(pl.members[k]);
+        // the finished instances go on behind the chunk (their own streams wait for it)
+        for (int i : done) {
+          state[i] = LS_RUN;
+          const hipError_t e = hipStreamWaitEvent(cs[i]->stream, bp.ev, 0);
+          const fde_status s2 = e != hipSuccess ? (fde_status)fail(FDE_EHIP, std::string("lockstep: ") +
+                                                                                   hipGetErrorString(e))
+                                                : post_readback(cs[i]);
           if (s2 != FDE_OK) drop(i, s2);
         }
-      const hipError_t he = hipStreamSynchronize(ls);
-      if (he != hipSuccess) {
-        st = (fde_status)fail(FDE_EHIP, std::string("lockstep batch: ") + hipGetErrorString(he));
-        break;
+        if (still.empty()) {
+          in_flight = false;
+        } else if (enqueued > maxit + kGraphIters) {
+          // every instance stops by its own iteration limit; this is a guard only
+          st = (fde_status)fail(FDE_EHIP, "batched PCG: done flags not set");
+        } else {
+          if (!done.empty()) {
+            full = false;
+            st = batch_subset(&bp, cs, still, ls);
+          }
+          const int chunk = next_chunk(still, enqueued);
+          if (st == FDE_OK) st = batch_chunk(&bp, full ? bp.full : bp.sub, full, chunk, ls);
+          enqueued += chunk;
+        }
+      } else if (q != hipErrorNotReady) {
+        st = (fde_status)fail(FDE_EHIP, std::string("lockstep batch: ") + hipGetErrorString(q));
       }
     }
-    // each phase's completion, in the order PCG -> update -> objective
-    for (int ph : {PH_PCG, PH_RES, PH_OBJ}) {
-      bool any = false;
-      for (int i = 0; i < n; ++i) {
-        if (!live[i] || R[i].phase != ph) continue;
-        const fde_status s2 = admm_advance(b->ctx[i], &R[i]);
-        any = true;
-        if (s2 < 0) drop(i, s2);
-        else if (R[i].phase == PH_DONE) drop(i, R[i].status);
-      }
-      const hipError_t he = any ? hipStreamSynchronize(ls) : hipSuccess;
-      if (he != hipSuccess) {
-        st = (fde_status)fail(FDE_EHIP, std::string("lockstep batch: ") + hipGetErrorString(he));
-        break;
-      }
+    for (int i = 0; i < n && st == FDE_OK; ++i) {
+      if (!live[i] || state[i] != LS_RUN) continue;
+      const int r = readback_ready(cs[i]);
+      if (r == 0) continue;
+      progress = true;
+      const fde_status s2 = r < 0 ? FDE_EHIP : admm_advance(cs[i], &R[i]);
+      if (s2 < 0 || R[i].phase == PH_DONE) drop(i, s2 < 0 ? s2 : R[i].status);
+      else if (R[i].phase == PH_PCG) state[i] = LS_WAIT;
     }
-    if (st != FDE_OK) break;
+    if (!progress) std::this_thread::yield();
   }
-  restore();
+  cleanup();
   return st;
 }
 }  // namespace
@@ -2332,3 +2405,4 @@ fde_status fde_pass_stats(fde_ctx* ctx, double* us, int32_t* launches, double* b
 }
 
 }  // extern "C"
+

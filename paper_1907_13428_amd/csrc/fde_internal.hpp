@@ -152,15 +152,82 @@ template <typename Args> struct BatchArgs {
   int count;
 };
 
+// Instance of launch block blk, wave-parallel: the active lanes of a wavefront
+// test first[base + lane + 1] <= blk for a window of instances at a time (the
+// lanes that hold form a prefix, so their count is the offset).  Called at
+// kernel entry by every thread of the block.  One load round per 64
+// instances, and the instance index stays wave-uniform (scalar), which also
+// keeps the argument table's field pointers recognisable as global memory.
 template <typename Args>
 __device__ __forceinline__ int batch_instance(const BatchArgs<Args>& b, int blk) {
-  int lo = 0, hi = b.count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (b.first[mid] <= blk) lo = mid;
-    else hi = mid - 1;
+  const int lane = (int)(threadIdx.x & 63);
+  const int width = __popcll(__ballot(1));
+  int base = 0;
+  for (;;) {
+    const int k = base + lane + 1;
+    const bool le = k < b.count && b.first[k] <= blk;
+    const int c = __popcll(__ballot(le));
+    if (c < width) return __builtin_amdgcn_readfirstlane(base + c);
+    base += width;
   }
-  return lo;
+}
+
+// A batched instance's arguments as the block's own copy, every field pointer
+// marked as global memory: pointers read from the argument table would
+// otherwise stay generic (each access through them a flat one) and be read
+// again from the table after each store.  The pointers are wave-uniform.
+template <typename T>
+__device__ __forceinline__ T* as_global(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  using G = __attribute__((address_space(1))) T*;
+  return (T*)(G)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ LinePassArgs batch_local(const LinePassArgs& s) {
+  LinePassArgs a = s;
+  a.in = as_global(a.in);
+  a.out = as_global(a.out);
+  a.lamA = as_global(a.lamA);
+  a.lamB = as_global(a.lamB);
+  a.tw = as_global(a.tw);
+  a.dplus = as_global(a.dplus);
+  a.dminus = as_global(a.dminus);
+  a.acc = as_global(a.acc);
+  a.oscale = as_global(a.oscale);
+  a.extra = as_global(a.extra);
+  a.escale = as_global(a.escale);
+  a.dotv = as_global(a.dotv);
+  a.partial = as_global(a.partial);
+  a.done = as_global(a.done);
+  return a;
+}
+
+__device__ __forceinline__ PrecondArgs batch_local(const PrecondArgs& s) {
+  PrecondArgs a = s;
+  a.r = as_global(a.r);
+  a.z = as_global(a.z);
+  a.spec = as_global(a.spec);
+  a.twx = as_global(a.twx);
+  a.twy = as_global(a.twy);
+  a.twt = as_global(a.twt);
+  a.lam_x = as_global(a.lam_x);
+  a.lam_y = as_global(a.lam_y);
+  a.lam_t = as_global(a.lam_t);
+  a.q = as_global(a.q);
+  a.xvec = as_global(a.xvec);
+  a.pvec = as_global(a.pvec);
+  a.scal = as_global(a.scal);
+  a.partial = as_global(a.partial);
+  a.partial2 = as_global(a.partial2);
+  a.done = as_global(a.done);
+  a.pq_partial = as_global(a.pq_partial);
+  a.rr_partial = as_global(a.rr_partial);
+  a.scal_w = as_global(a.scal_w);
+  a.ints = as_global(a.ints);
+  a.rzs_partial = as_global(a.rzs_partial);
+  return a;
 }
 
 // A recorded pass launch (the host records an instance's PCG iteration once,

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
 template <int L, typename TS, bool FUSE>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd_b(BatchArgs<PrecondArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  pre_xfwd_body<L, TS, FUSE>(b.args[i], blockIdx.x - b.first[i]);
+  pre_xfwd_body<L, TS, FUSE>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,7 +349,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc(PrecondArgs a) {
 template <int L, typename TS, int MODE, int SIGN, int S>
 __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc_b(BatchArgs<PrecondArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  pre_cc_body<L, TS, MODE, SIGN, S>(b.args[i], blockIdx.x - b.first[i], b.first[i + 1] - b.first[i]);
+  pre_cc_body<L, TS, MODE, SIGN, S>(batch_local(b.args[i]), blockIdx.x - b.first[i], b.first[i + 1] - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
 template <int L, typename TS, int OUT>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xinv_b(BatchArgs<PrecondArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  pre_xinv_body<L, TS, OUT>(b.args[i], blockIdx.x - b.first[i]);
+  pre_xinv_body<L, TS, OUT>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kLineThreads) void k_xpass(LinePassArgs a) {
 template <int L, bool VAR, bool TRANS, bool PAD = false>
 __global__ __launch_bounds__(kLineThreads) void k_xpass_b(BatchArgs<LinePassArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  xpass_body<L, VAR, TRANS, PAD>(b.args[i], blockIdx.x - b.first[i]);
+  xpass_body<L, VAR, TRANS, PAD>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,7 +401,8 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass(LinePassArgs a) {
 template <int L, bool VAR, bool TRANS, int S, bool COL = false, bool PAD = false>
 __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass_b(BatchArgs<LinePassArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  ypass_body<L, VAR, TRANS, S, COL, PAD>(b.args[i], blockIdx.x - b.first[i], b.first[i + 1] - b.first[i]);
+  ypass_body<L, VAR, TRANS, S, COL, PAD>(batch_local(b.args[i]), blockIdx.x - b.first[i],
+                                         b.first[i + 1] - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------

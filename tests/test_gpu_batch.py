@@ -127,23 +127,16 @@ def max_rel(a, b):
     return float(np.max(np.abs(a - b))) / (nb if nb > 0 else 1.0)
 
 
-# The batched pass kernels run the single kernels' code on arguments read from
-# a table; the compiler may round a few operations differently there (measured
-# in FP64: a few ulps, <= 1.4e-15 relative after six ADMM iterations), so the
-# lockstep run is compared with the per-instance solves to 1e-12, with equal
-# counts.  With the FP32 preconditioner the same few-ulp differences are float
-# ulps inside the preconditioner, which the FP64 PCG absorbs to its tolerance:
-# the bar is that of the PCG parity cases, 1e-9.
-LOCKSTEP_BAR = 1e-12
-LOCKSTEP_BAR_FP32 = 1e-9
-
-
+# The batched pass kernels run the single kernels' code, with each instance's
+# arguments read from a table into the block's own copy and that instance's
+# block decomposition: the lockstep run equals the per-instance solves bit for
+# bit, FP64 and FP32 preconditioner alike.
 @pytest.mark.parametrize("fp32", [0, 1])
 def test_batch_lockstep_equals_sequential_and_oracle(fp32):
     """Lockstep mode (the Krylov iterations of all instances as batched pass
     launches): uneven instances with different ADMM budgets take the same
     Krylov and ADMM iteration counts as the per-instance solves and the same
-    iterates to rounding, and follow the oracle."""
+    iterates bit for bit, and follow the oracle."""
     banner("batch lockstep vs sequential", fp32)
     ws = batchable(maxit=6)
     a, sa, ca = run_mode(ws, "lockstep", fp32)
@@ -152,9 +145,8 @@ def test_batch_lockstep_equals_sequential_and_oracle(fp32):
     for i in range(len(ws)):
         assert sa[i]["admm_iters"] == sb[i]["admm_iters"] == ws[i].admm_maxit
         assert sa[i]["pcg_total"] == sb[i]["pcg_total"]
-        bar = LOCKSTEP_BAR_FP32 if fp32 else LOCKSTEP_BAR
         for k in a[i]:
-            assert max_rel(a[i][k], b[i][k]) <= bar, (i, k, max_rel(a[i][k], b[i][k]))
+            assert np.array_equal(a[i][k], b[i][k]), (i, k, max_rel(a[i][k], b[i][k]))
     for i in (0, 3):
         ref = admm.admm_solve(ws[i], iters=ws[i].admm_maxit)
         for k in ("y", "u", "p"):
@@ -176,7 +168,7 @@ def test_batch_lockstep_converging_instances():
     for i in range(len(ws)):
         assert sa[i]["admm_iters"] == sb[i]["admm_iters"]
         for k in a[i]:
-            assert max_rel(a[i][k], b[i][k]) <= LOCKSTEP_BAR, (i, k)
+            assert np.array_equal(a[i][k], b[i][k]), (i, k, max_rel(a[i][k], b[i][k]))
 
 
 def test_batch_lockstep_falls_back_without_batched_passes():
