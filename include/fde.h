@@ -356,8 +356,9 @@ fde_status fde_autotune(fde_ctx* ctx, int32_t* choices);
  * instances advance one ADMM iteration at a time together.  Instances whose
  * x-step has no batched form (MINRES, a fractional time order, lengths
  * without batched pass variants) make the call run the concurrent mode
- * instead.  Results equal the single solves' up to the order of the partial
- * sums in the fused dot products (a few units in the last place).
+ * instead.  Instances whose x-step has converged leave the batched launches
+ * and go on with their own phases on their own streams while the others
+ * iterate.  Results equal the single solves' bit for bit.
  * Arrays indexed by instance: yhat[i], g[i] (g may be NULL, or g[i] NULL),
  * and the iterate fields y[i] .. wu[i] (device fields of instance i's size,
  * read as the starting point, overwritten).  The caller makes the inputs
