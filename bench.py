@@ -351,20 +351,12 @@ def paper_tables_leg(fde, torch):
     return {"rows": rows, "paper_times": rec["time_note"]}
 
 
-def batched_leg(fde, torch, cap):
-    """64 uneven instances (sizes 64..512, nt 16/32, random orders and gamma, GRF
-    targets), each run for `cap` ADMM iterations: in lockstep (the Krylov
-    iterations of all instances as batched pass launches, one graph), in the
-    stream-per-instance concurrent mode, both FP64 and with the FP32
-    preconditioner, and sequentially in FP64."""
-    import workloads as W
-
-    ws = W.batched()
+def batch_modes(fde, torch, ws, cap, modes):
+    """Time fde_batch_solve over the instances ws (each run for `cap` ADMM
+    iterations) in each (tag, fp32, mode) of `modes`."""
     yh = [torch.from_numpy(w.yhat).to("cuda") for w in ws]
     rec = {"instances": len(ws), "points": sum(w.N for w in ws), "admm_iters_per_instance": cap}
-    for tag, fp32, mode in (("lockstep_fp32_precond", 1, "lockstep"), ("lockstep_fp64", 0, "lockstep"),
-                            ("concurrent_fp32_precond", 1, "concurrent"), ("concurrent_fp64", 0, "concurrent"),
-                            ("sequential_fp64", 0, "sequential")):
+    for tag, fp32, mode in modes:
         probs, prms = zip(*[fde.from_workload(w, precond_fp32=fp32, admm_maxit=cap) for w in ws])
         with fde.Batch(list(probs), list(prms)) as b:
             torch.cuda.synchronize()
@@ -374,11 +366,40 @@ def batched_leg(fde, torch, cap):
         pcg = sum(s["pcg_total"] for s in stats)
         rec[tag] = {"s": round(dt, 3), "solves_per_s": round(len(ws) / dt, 2), "pcg_iters_per_s": round(pcg / dt, 1),
                     "pcg_total": pcg}
+    return rec
+
+
+def batched_leg(fde, torch, cap):
+    """64 uneven instances (sizes 64..512, nt 16/32, random orders and gamma, GRF
+    targets), each run for `cap` ADMM iterations: in lockstep (the Krylov
+    iterations of all instances as batched pass launches), in the
+    stream-per-instance concurrent mode, both FP64 and with the FP32
+    preconditioner, and sequentially in FP64."""
+    import workloads as W
+
+    rec = batch_modes(fde, torch, W.batched(), cap,
+                      (("lockstep_fp32_precond", 1, "lockstep"), ("lockstep_fp64", 0, "lockstep"),
+                       ("concurrent_fp32_precond", 1, "concurrent"), ("concurrent_fp64", 0, "concurrent"),
+                       ("sequential_fp64", 0, "sequential")))
     # the batched form alone (FP64 both ways), and with the FP32 preconditioner; the
     # stream-per-instance concurrent mode beside it
     rec["speedup_lockstep_fp64"] = round(rec["sequential_fp64"]["s"] / rec["lockstep_fp64"]["s"], 3)
     rec["speedup_concurrency_fp64"] = round(rec["sequential_fp64"]["s"] / rec["concurrent_fp64"]["s"], 3)
     rec["speedup"] = round(rec["sequential_fp64"]["s"] / rec["lockstep_fp32_precond"]["s"], 3)
+    return rec
+
+
+def batched_small_leg(fde, torch, cap):
+    """256 small uneven instances (16..64 nodes per axis, nt 8/16; 4.4 M points in
+    all), each run for `cap` ADMM iterations, FP64: lockstep, concurrent and
+    sequential."""
+    import workloads as W
+
+    rec = batch_modes(fde, torch, W.batched_small(), cap,
+                      (("lockstep_fp64", 0, "lockstep"), ("concurrent_fp64", 0, "concurrent"),
+                       ("sequential_fp64", 0, "sequential")))
+    rec["speedup_lockstep_fp64"] = round(rec["sequential_fp64"]["s"] / rec["lockstep_fp64"]["s"], 3)
+    rec["speedup_concurrency_fp64"] = round(rec["sequential_fp64"]["s"] / rec["concurrent_fp64"]["s"], 3)
     return rec
 
 
@@ -553,6 +574,8 @@ def main():
     if not a.no_batch:
         progress("batched instances")
         out["batched"] = batched_leg(fde, torch, a.batch_cap)
+        progress("batched small instances")
+        out["batched_small"] = batched_small_leg(fde, torch, a.batch_cap)
 
     out["config"] = {"workload": "headline_256x256x64", "nx": 256, "ny": 256, "nt": 64, "alpha": 1.3, "beta": 1.7,
                      "gamma": 1e-6, "delta": 1.0, "rho": 1.0, "krylov_tol": 1e-10, "admm_tol": 1e-6,

@@ -151,6 +151,8 @@ typedef struct {
   double t_krylov;        /* the x-step's Krylov solve (step 2)                  */
   double t_update;        /* B y, recovery of p and u, box projection, dual
                              updates and residual maxima (steps 3-6)            */
+  int32_t batched;        /* 1: the Krylov iterations ran as batched launches
+                             (fde_batch_solve, lockstep mode); 0 otherwise     */
 } fde_admm_stats;
 
 /* Check a problem/parameter pair without touching the GPU.  FDE_OK or

@@ -1917,6 +1917,7 @@ fde_status batch_lockstep(fde_batch* b, const double* const* yhat, const double*
   for (int i = 0; i < n; ++i) {
     res[i] = admm_begin(cs[i], &R[i], yhat[i], g ? g[i] : nullptr, y[i], u[i], zy[i], zu[i], p[i], wy[i], wu[i],
                         true);
+    R[i].st.batched = 1;
     maxit = std::max(maxit, cs[i]->prm.krylov_maxit);
     if (res[i] >= 0) {
       live[i] = 1;

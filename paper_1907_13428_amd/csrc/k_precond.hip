@@ -448,9 +448,10 @@ __global__ __launch_bounds__(kPreThreads) void k_pre_xinv_b(BatchArgs<PrecondArg
 // dispatch
 // ---------------------------------------------------------------------------
 // Lengths whose PCG passes have batched twins: the axis lengths of the batched
-// workload's grids (64 .. 512 nodes in space, 16 and 32 time levels)
+// workloads' grids (8 .. 512 nodes in space and time, radix 2 and 3)
 constexpr bool batch_dim(int n) {
-  return n == 16 || n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
+  return n == 8 || n == 16 || n == 24 || n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 192 ||
+         n == 256 || n == 384 || n == 512;
 }
 using PreBatchKernel = void (*)(BatchArgs<PrecondArgs>);
 template <int L, typename TS, bool FUSE> static PreBatchKernel xfwd_twin() {

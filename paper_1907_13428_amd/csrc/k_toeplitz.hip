@@ -413,9 +413,10 @@ __global__ __launch_bounds__((YCfg<L, S>::NT)) void k_ypass_b(BatchArgs<LinePass
 
 
 // Lengths whose constant-coefficient passes have batched twins: the FFT
-// lengths of the batched workload's grids (64 .. 512 nodes per axis)
+// lengths of the batched workloads' grids (16 .. 512 nodes per axis)
 constexpr bool batch_embed(int L) {
-  return L == 128 || L == 192 || L == 256 || L == 384 || L == 512 || L == 768 || L == 1024;
+  return L == 32 || L == 48 || L == 64 || L == 96 || L == 128 || L == 192 || L == 256 || L == 384 || L == 512 ||
+         L == 768 || L == 1024;
 }
 using LineBatchKernel = void (*)(BatchArgs<LinePassArgs>);
 

@@ -60,7 +60,7 @@ class Stats(ctypes.Structure):
                 ("pcg_max", ctypes.c_int32), ("r_p", ctypes.c_double), ("r_y", ctypes.c_double),
                 ("r_u", ctypes.c_double), ("J", ctypes.c_double), ("t_total", ctypes.c_double),
                 ("t_pcg", ctypes.c_double), ("dual_inf", ctypes.c_double), ("t_rhs", ctypes.c_double),
-                ("t_krylov", ctypes.c_double), ("t_update", ctypes.c_double)]
+                ("t_krylov", ctypes.c_double), ("t_update", ctypes.c_double), ("batched", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -96,14 +96,14 @@ def test_batch_mixed_methods_concurrent_equals_sequential_and_oracle():
             assert rel(a[i][k], getattr(ref, k)) <= 1e-7, (i, k)
 
 
-def batchable(count=4, seed=21, maxit=None):
-    """Uneven instances on lengths with batched passes (64, 96, 128 nodes in
-    space; 16 and 32 time levels)."""
+def batchable(count=4, seed=21, maxit=None, sizes=(64, 96, 128), nts=(16, 32)):
+    """Uneven instances on lengths with batched passes (by default 64, 96, 128
+    nodes in space; 16 and 32 time levels)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for i in range(count):
-        nx, ny = int(rng.choice([64, 96, 128])), int(rng.choice([64, 96, 128]))
-        nt = int(rng.choice([16, 32]))
+        nx, ny = int(rng.choice(sizes)), int(rng.choice(sizes))
+        nt = int(rng.choice(nts))
         w = W.small_mixed(nx=nx, ny=ny, nt=nt).replace(alpha=float(rng.uniform(1.1, 1.9)),
                                                        beta=float(rng.uniform(1.1, 1.9)),
                                                        gamma=float(10 ** rng.uniform(-5, -3)))
@@ -142,6 +142,7 @@ def test_batch_lockstep_equals_sequential_and_oracle(fp32):
     a, sa, ca = run_mode(ws, "lockstep", fp32)
     b, sb, cb = run_mode(ws, "sequential", fp32)
     assert ca == cb
+    assert all(s["batched"] == 1 for s in sa) and all(s["batched"] == 0 for s in sb)
     for i in range(len(ws)):
         assert sa[i]["admm_iters"] == sb[i]["admm_iters"] == ws[i].admm_maxit
         assert sa[i]["pcg_total"] == sb[i]["pcg_total"]
@@ -151,6 +152,22 @@ def test_batch_lockstep_equals_sequential_and_oracle(fp32):
         ref = admm.admm_solve(ws[i], iters=ws[i].admm_maxit)
         for k in ("y", "u", "p"):
             assert rel(a[i][k], getattr(ref, k)) <= 1e-7, (i, k)
+
+
+def test_batch_lockstep_small_instances():
+    """Many small uneven grids (16 .. 48 nodes in space, 8 and 16 time levels,
+    the regime where single launches cannot fill the GPU): the lockstep run
+    equals the per-instance solves bit for bit."""
+    banner("batch lockstep small instances")
+    ws = batchable(count=12, seed=33, maxit=4, sizes=(16, 24, 32, 48), nts=(8, 16))
+    a, sa, ca = run_mode(ws, "lockstep")
+    b, sb, cb = run_mode(ws, "sequential")
+    assert ca == cb
+    assert all(s["batched"] == 1 for s in sa)
+    for i in range(len(ws)):
+        assert sa[i]["pcg_total"] == sb[i]["pcg_total"] and sa[i]["admm_iters"] == sb[i]["admm_iters"]
+        for k in a[i]:
+            assert np.array_equal(a[i][k], b[i][k]), (i, k, max_rel(a[i][k], b[i][k]))
 
 
 def test_batch_lockstep_converging_instances():
@@ -164,6 +181,7 @@ def test_batch_lockstep_converging_instances():
     a, sa, ca = run_mode(ws, "lockstep")
     b, sb, cb = run_mode(ws, "sequential")
     assert ca == cb
+    assert all(s["batched"] == 1 for s in sa)
     assert len({s["admm_iters"] for s in sb}) > 1  # the instances stop at different iterations
     for i in range(len(ws)):
         assert sa[i]["admm_iters"] == sb[i]["admm_iters"]
@@ -179,6 +197,7 @@ def test_batch_lockstep_falls_back_without_batched_passes():
     ws = [w.replace(admm_tol=0.0, admm_maxit=8) for w in ws]
     a, sa, _ = run_mode(ws, "lockstep")
     b, sb, _ = run_mode(ws, "sequential")
+    assert all(s["batched"] == 0 for s in sa)  # the concurrent mode ran
     for i in range(len(ws)):
         for k in a[i]:
             assert np.array_equal(a[i][k], b[i][k]), (i, k)

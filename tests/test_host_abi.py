@@ -161,3 +161,36 @@ def test_product_path_has_no_cpu_fallback():
     prob, prm = fde.from_workload(w)
     with pytest.raises(RuntimeError):
         fde.Context(prob, prm)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of fde_problem, fde_admm_params and fde_admm_stats
+    have the C header's sizes and field offsets (compiled with the host C
+    compiler)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"fde_problem": fde.Problem, "fde_admm_params": fde.Params, "fde_admm_stats": fde.Stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "fde.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        cls = structs[cname]
+        want = ctypes.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(val) == want, (cname, field, int(val), want)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())

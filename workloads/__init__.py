@@ -245,9 +245,10 @@ def paper_test(n=16, alpha_t=0.7, beta=1.3, gamma=1e-4, ya=-4.0, ua=-350.0, delt
 BATCH_SIZES = (64, 96, 128, 192, 256, 384, 512)
 
 
-def batched(count=64, seed=BASE_SEED + 4, sizes=BATCH_SIZES, nts=(16, 32)) -> List[Workload]:
+def batched(count=64, seed=BASE_SEED + 4, sizes=BATCH_SIZES, nts=(16, 32),
+            target_seed=BASE_SEED + 4) -> List[Workload]:
     """Uneven instances: nx, ny from `sizes`, nt from `nts`, orders ~ U[1.1, 1.9],
-    log10 gamma ~ U[-6, -3], GRF target (seed base+4+i), |u| <= 1."""
+    log10 gamma ~ U[-6, -3], GRF target (seed target_seed+i), |u| <= 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for i in range(count):
@@ -259,9 +260,19 @@ def batched(count=64, seed=BASE_SEED + 4, sizes=BATCH_SIZES, nts=(16, 32)) -> Li
         gamma = float(10 ** rng.uniform(-6, -3))
         w = Workload(name=f"batch{i}_{nx}x{ny}x{nt}", nx=nx, ny=ny, nt=nt, alpha=a, beta=b,
                      gamma=gamma, ua=-1.0, ub=1.0)
-        w.yhat = target_grf(nx, ny, nt, BASE_SEED + 4 + i)
+        w.yhat = target_grf(nx, ny, nt, target_seed + i)
         out.append(w)
     return out
+
+
+BATCH_SMALL_SIZES = (16, 24, 32, 48, 64)
+
+
+def batched_small(count=256) -> List[Workload]:
+    """Many small uneven instances, drawn as in batched(): 16 .. 64 nodes per
+    axis, nt 8 or 16 (single launches of such grids cannot fill the GPU)."""
+    return batched(count=count, seed=BASE_SEED + 5, sizes=BATCH_SMALL_SIZES, nts=(8, 16),
+                   target_seed=BASE_SEED + 1000)
 
 
 def random_field(shape, seed):
