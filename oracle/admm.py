@@ -41,7 +41,7 @@ from typing import Optional
 import numpy as np
 
 from . import operator as op
-from .precond import apply_precond, precond_tables
+from .precond import apply_precond, apply_precond_scaled, diag_S, precond_tables, scaling_factor
 
 
 @dataclasses.dataclass
@@ -279,7 +279,14 @@ def admm_solve(w, *, iters: Optional[int] = None, solver: Optional[str] = None,
         Schol = np.linalg.cholesky(S)
 
     A = lambda v: apply_S(d, sc, v)
-    M = lambda v: apply_precond(tab, v)
+    if getattr(w, "precond_kind", 0) == 2:
+        # Delta S~^{-1} Delta: the diagonal scaling for variable coefficients
+        if solver == "minres":
+            raise ValueError("precond_kind 2 is a PCG preconditioner")
+        delta_s = scaling_factor(diag_S(w, d, sc.My, sc.Mp, sc.psi))
+        M = lambda v: apply_precond_scaled(tab, delta_s, v)
+    else:
+        M = lambda v: apply_precond(tab, v)
     pcg_counts = []
     maxit = w.admm_maxit if iters is None else iters
     r_p = r_y = r_u = math.inf

@@ -14,6 +14,15 @@ Sec. 3.2.2, eq. (3.11): the matching approximation with the same blocks,
     S^ = D^ M2~^{-1} D^*,  D^ = C_3(B)^* + (M1~ M2~)^{1/2},  M1~ = a, M2~ = mbar_p,
 is a circulant too, with eigenvalues |Lambda + sqrt(a mbar_p)|^2 / mbar_p
 (precond_kind = 1).
+Variable coefficients (the remark closing Sec. 4: circulants lose effect when
+the coefficients vary, and a diagonal-times-structured form is the remedy the
+paper points to) -- precond_kind = 2, this build's reading: the symmetric
+diagonal scaling of S~,
+    P^{-1} = Delta S~^{-1} Delta,  Delta = (s0 / diag(S))^{1/2},
+with diag(S) the exact diagonal of S = M_y + B^T M_p^{-1} B (eq. (3.9)) and s0
+its mean over the grid (any constant gives the same PCG iterates).  Delta
+carries the coefficient field's local size into the preconditioner; the
+circulant keeps the mean-coefficient spectrum.
 
 DFT convention: lambda_k = sum_m c_m exp(-2 pi i k m / n), computed here by the
 explicit O(n^2) sum; the circulant acts as C x = F^{-1} diag(lambda) F x with
@@ -116,3 +125,26 @@ def apply_precond(tab, r: np.ndarray) -> np.ndarray:
     Z = np.matmul(np.conj(Fy), Z) / ny
     Z = Z @ np.conj(Fx).T / nx
     return Z.real.copy()
+
+
+def diag_S(w, d: Disc, My, Mp, psi) -> np.ndarray:
+    """Diagonal of S = M_y + B^T M_p^{-1} B with B = psi D (eq. (3.9), scaled
+    form), as a field (nt, ny, nx): S_ii = M_y(t_i) + psi^2 sum_r D[r, i]^2 /
+    M_p(t_r), the sum over the entries of column i of the assembled D
+    (eq. (4.9)).  My, Mp: per time slice."""
+    from .operator import assemble_D_sparse
+
+    plane = d.nx * d.ny
+    D = assemble_D_sparse(d)
+    col = (D.multiply(D)).T @ np.repeat(1.0 / np.asarray(Mp, dtype=np.float64), plane)
+    return (np.repeat(np.asarray(My, dtype=np.float64), plane) + psi ** 2 * col).reshape(d.nt, d.ny, d.nx)
+
+
+def scaling_factor(dS: np.ndarray) -> np.ndarray:
+    """Delta = (s0 / diag S)^{1/2}, s0 the mean of diag S (precond_kind = 2)."""
+    return np.sqrt(float(np.mean(dS)) / dS)
+
+
+def apply_precond_scaled(tab, delta: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = Delta S~^{-1} Delta r (precond_kind = 2)."""
+    return delta * apply_precond(tab, delta * r)

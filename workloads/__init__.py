@@ -58,7 +58,8 @@ class Workload:
     prox: int = 0  # 0: Algorithm 1; 1: generalized ADMM (Algorithm 2), R_y = c_y I - J1, R_u = c_u I - J2
     prox_cy: float = 0.0  # c_y (0: the smallest admissible, max diag J1)
     prox_cu: float = 0.0  # c_u (0: the smallest admissible, max diag J2)
-    precond_kind: int = 0  # 0: S~ of eq. (3.10); 1: the matching approximation S^ of eq. (3.11)
+    precond_kind: int = 0  # 0: S~ of eq. (3.10); 1: the matching approximation S^ of eq. (3.11);
+    #                        2: S~ with the diagonal scaling Delta S~^{-1} Delta (variable coefficients)
     krylov_solver: int = 0  # 0: PCG on the normal equations; 1: MINRES on the merged system with K~
     yhat: Optional[np.ndarray] = None  # (nt, ny, nx)
     dplus: Optional[np.ndarray] = None  # (ny, nx) or None (= 1)
