@@ -116,7 +116,13 @@ typedef struct {
                              1: the matching approximation S^ of eq. (3.11)
                              with the same blocks, (C^* + c)(C + c) / mbar_p,
                              c = (a mbar_p)^{1/2} (C the 3-level T. Chan
-                             circulant of B, eq. (5.2))                       */
+                             circulant of B, eq. (5.2));
+                             2: S~ with a diagonal scaling for variable
+                             coefficients (the remark closing Sec. 4 points to
+                             diagonal-times-structured forms): the inverse is
+                             Delta S~^{-1} Delta, Delta = (s0 / diag S)^{1/2}
+                             with the exact diagonal of S (eq. (3.9)) and s0
+                             its mean; PCG x-step only (krylov_solver 0) */
   int32_t krylov_solver;  /* x-step solver: 0: PCG on the normal equations
                              (3.9) with S~ (or S^); 1: MINRES on the merged
                              saddle-point system (3.8) with the block-diagonal
@@ -169,6 +175,13 @@ fde_status fde_validate(const fde_problem* prob, const fde_admm_params* prm);
  * Any output pointer may be NULL. */
 fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, double* scal,
                            double* lam_x, double* lam_y, double* lam_t, double* gx, double* gy);
+
+/* Host-only: the diagonal scaling Delta of precond_kind 2 (whatever prm's
+ * precond_kind), written to delta (host, caller-allocated, nx*ny*nt values,
+ * field layout).  diag S = M_y + psi^2 (sum of the squared entries of the
+ * column of D, each over M_p of its row's time level) (eq. (3.9), (4.9)).
+ * FDE_EINVAL on invalid arguments.  O(nx^2 ny + ny^2 nx) host work. */
+fde_status fde_host_diag_scaling(const fde_problem* prob, const fde_admm_params* prm, double* delta);
 
 /* Create a context on the current HIP device.  `stream` is a hipStream_t
  * (NULL = default stream).  Validates, builds the weights, embedding and

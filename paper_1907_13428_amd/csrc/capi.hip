@@ -118,6 +118,10 @@ struct fde_ctx {
   bool ycol = false;  // coefficient fields constant along y: per-column y-pass multipliers
   double *dplus = nullptr, *dminus = nullptr;
   double *invMp = nullptr, *My = nullptr, *Mu = nullptr, *Mp = nullptr, *wts = nullptr, *ones = nullptr;
+  // precond_kind 2: the table A(x, y) and per-slice (alpha', beta') of the diagonal
+  // scaling (allocated when that kind is first used)
+  double* dsA = nullptr;
+  double2* dsab = nullptr;
   double2 *dxA = nullptr, *dxB = nullptr, *dyA = nullptr, *dyB = nullptr;  // dL/dalpha, dL/dbeta
 
   // workspace fields
@@ -358,6 +362,10 @@ fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
   a.scal = c->scal;
   a.tile_y = c->tile_pre_y;
   a.tile_t = c->tile_pre_t;
+  if (c->prm.precond_kind == 2) {
+    a.ds_a = c->dsA;
+    a.ds_ab = c->dsab;
+  }
   return a;
 }
 
@@ -1064,6 +1072,16 @@ fde_status upload_admm_tables(fde_ctx* c) {
   HIP_TRY(hipMemcpy(c->Mu, s.Mu.data(), bytes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->Mp, s.Mp.data(), bytes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->wts, s.wts.data(), bytes, hipMemcpyHostToDevice));
+  if (c->prm.precond_kind == 2) {
+    if (!c->dsA) {
+      HIP_TRY(c->alloc(&c->dsA, s.dsA.size()));
+      HIP_TRY(hipMemcpy(c->dsA, s.dsA.data(), sizeof(double) * s.dsA.size(), hipMemcpyHostToDevice));
+      HIP_TRY(c->alloc(&c->dsab, (size_t)c->nt));
+    }
+    std::vector<double2> ab(c->nt);
+    for (int t = 0; t < c->nt; ++t) ab[t] = double2{s.ds_alpha[t], s.ds_beta[t]};
+    HIP_TRY(hipMemcpy(c->dsab, ab.data(), sizeof(double2) * ab.size(), hipMemcpyHostToDevice));
+  }
   return FDE_OK;
 }
 
@@ -1118,6 +1136,8 @@ struct SliceOps {
     a.psi = 1.0;
     a.inv_n = 1.0 / (double)plane;
     a.div_mode = 1;
+    a.ds_a = nullptr;  // the transposed slice operator's own circulant, no scaling of S
+    a.ds_ab = nullptr;
     return fde::launch_precond(a, c->fp32, c->stream, nullptr, nullptr);
   }
   hipError_t dots(int count, const double* const* a, const double* const* b) {
@@ -1434,6 +1454,22 @@ fde_status fde_host_tables(const fde_problem* prob, const fde_admm_params* prm, 
   put(lam_t, s.tchan_t);
   if (gx) std::memcpy(gx, s.x.g.data(), sizeof(double) * s.x.g.size());
   if (gy) std::memcpy(gy, s.y.g.data(), sizeof(double) * s.y.g.size());
+  return FDE_OK;
+}
+
+fde_status fde_host_diag_scaling(const fde_problem* prob, const fde_admm_params* prm, double* delta) {
+  if (!prm || !delta) return (fde_status)fail(FDE_EINVAL, "fde_host_diag_scaling: null argument");
+  fde_admm_params q = *prm;
+  q.precond_kind = 2;
+  q.krylov_solver = 0;
+  fde::host::Setup s;
+  std::string msg;
+  const int st = fde::host::build_setup(prob, &q, &s, &msg);
+  if (st != FDE_OK) return (fde_status)fail(st, msg);
+  const size_t plane = (size_t)s.nx * s.ny;
+  for (int t = 0; t < s.nt; ++t)
+    for (size_t k = 0; k < plane; ++k)
+      delta[(size_t)t * plane + k] = 1.0 / std::sqrt(s.ds_alpha[t] + s.ds_beta[t] * s.dsA[k]);
   return FDE_OK;
 }
 

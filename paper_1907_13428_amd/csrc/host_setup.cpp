@@ -63,8 +63,12 @@ int validate_params(const fde_admm_params* q, std::string* msg) {
   if (q->pcg_cold_start != 0 && q->pcg_cold_start != 1) { *msg = "pcg_cold_start must be 0 or 1"; return FDE_EINVAL; }
   if (q->tol_mode != 0 && q->tol_mode != 1) { *msg = "tol_mode must be 0 or 1"; return FDE_EINVAL; }
   if (q->prox != 0 && q->prox != 1) { *msg = "prox must be 0 or 1"; return FDE_EINVAL; }
-  if (q->precond_kind != 0 && q->precond_kind != 1) { *msg = "precond_kind must be 0 or 1"; return FDE_EINVAL; }
+  if (q->precond_kind < 0 || q->precond_kind > 2) { *msg = "precond_kind must be 0, 1 or 2"; return FDE_EINVAL; }
   if (q->krylov_solver != 0 && q->krylov_solver != 1) { *msg = "krylov_solver must be 0 or 1"; return FDE_EINVAL; }
+  if (q->precond_kind == 2 && q->krylov_solver != 0) {
+    *msg = "precond_kind 2 (diagonally scaled S~) is a preconditioner of the PCG x-step (krylov_solver 0)";
+    return FDE_EINVAL;
+  }
   if (q->prox) {
     // Algorithm 2 takes its step in (0, 1]; R_y, R_u must not be indefinite
     if (!(q->rho <= 1.0)) { *msg = "prox = 1 (Algorithm 2) needs rho in (0, 1]"; return FDE_EINVAL; }
@@ -284,6 +288,74 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
   s->inv_mbar = 1.0 / mbar;
   // eq. (3.11): |L + (a mbar)^{1/2}|^2 / mbar = a + |L|^2 / mbar + 2 (a / mbar)^{1/2} Re L
   s->match2 = q->precond_kind == 1 ? 2.0 * std::sqrt(s->a / mbar) : 0.0;
+  // precond_kind 2: column (x, t) of B = psi D holds psi ct[t'-t] at the same
+  // node of every later level t' and the spatial column at level t, so
+  // diag(S) = My(t) + psi^2 (sum_{t'>t} ct[t'-t]^2 / Mp(t') + A(x, y) / Mp(t))
+  s->ds_alpha.clear();
+  s->ds_beta.clear();
+  if (q->precond_kind == 2) {
+    if (s->dsA.empty()) diag_scaling_table(s);
+    const double psi2 = s->psi * s->psi;
+    s->ds_alpha.assign(nt, 0.0);
+    s->ds_beta.assign(nt, 0.0);
+    long double meanA = 0;
+    for (double v : s->dsA) meanA += v;
+    meanA /= (long double)s->dsA.size();
+    long double s0 = 0;
+    for (int t = 0; t < nt; ++t) {
+      long double later = 0;
+      for (int t2 = t + 1; t2 < nt; ++t2) later += (long double)s->ct[t2 - t] * s->ct[t2 - t] / s->Mp[t2];
+      s->ds_alpha[t] = (double)(s->My[t] + psi2 * later);
+      s->ds_beta[t] = psi2 / s->Mp[t];
+      s0 += s->ds_alpha[t] + s->ds_beta[t] * meanA;
+    }
+    s0 /= nt;
+    for (int t = 0; t < nt; ++t) {
+      s->ds_alpha[t] = (double)(s->ds_alpha[t] / s0);
+      s->ds_beta[t] = (double)(s->ds_beta[t] / s0);
+    }
+  }
+}
+
+void diag_scaling_table(Setup* s) {
+  // A(x, y) = (ct[0] - Lx_ii - Ly_ii)^2 + sum_{r != i} Lx[r, i]^2 + sum_{r != i} Ly[r, i]^2,
+  // with Lx[r, i] = cx (d+(r) G[r, i] + d-(r) G[i, r]) along the x-line of the node
+  // (eq. (4.6)-(4.7); G[r, i] = g_{r-i+1} for r >= i-1) and Ly the same along y
+  const int nx = s->nx, ny = s->ny;
+  auto dp = [&](int i, int j) { return s->var ? s->dplus[(size_t)j * nx + i] : 1.0; };
+  auto dm = [&](int i, int j) { return s->var ? s->dminus[(size_t)j * nx + i] : 1.0; };
+  // entry (r, i) of a line operator: coefficients at row r
+  auto entry = [](const AxisTables& ax, int r, int i, double cp, double cm) {
+    const int a = r - i + 1, b = i - r + 1;
+    const double gr = a >= 0 ? ax.g[a] : 0.0, gi = b >= 0 ? ax.g[b] : 0.0;
+    return ax.c * (cp * gr + cm * gi);
+  };
+  std::vector<double> off((size_t)nx * ny, 0.0), dia((size_t)nx * ny, 0.0);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      long double acc = 0;
+      for (int r = 0; r < nx; ++r) {
+        const double v = entry(s->x, r, i, dp(r, j), dm(r, j));
+        if (r == i) dia[(size_t)j * nx + i] += v;
+        else acc += (long double)v * v;
+      }
+      off[(size_t)j * nx + i] += (double)acc;
+    }
+  for (int i = 0; i < nx; ++i)
+    for (int j = 0; j < ny; ++j) {
+      long double acc = 0;
+      for (int r = 0; r < ny; ++r) {
+        const double v = entry(s->y, r, j, dp(i, r), dm(i, r));
+        if (r == j) dia[(size_t)j * nx + i] += v;
+        else acc += (long double)v * v;
+      }
+      off[(size_t)j * nx + i] += (double)acc;
+    }
+  s->dsA.resize((size_t)nx * ny);
+  for (size_t k = 0; k < s->dsA.size(); ++k) {
+    const double d0 = s->ct[0] - dia[k];
+    s->dsA[k] = d0 * d0 + off[k];
+  }
 }
 
 int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::string* msg) {

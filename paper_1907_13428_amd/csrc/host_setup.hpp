@@ -44,6 +44,11 @@ struct Setup {
   std::vector<cd> lam_t, lam_tT, tw_t_emb;  // Lt-point embedding eigenvalues of C_t, C_t^T (with 1/Lt), twiddles
   std::vector<double> wts, My, Mu, Mp, invMp;  // per time slice
   std::vector<double> dplus, dminus;   // (ny*nx) copies when var
+  // precond_kind 2: diag(S) = alpha_t + beta_t A(x, y) (eq. (3.9) in the psi-scaled
+  // form), A the spatial part of the squared column norms of D; the kernels scale
+  // by Delta = (alpha'_t + beta'_t A)^{-1/2}, primes: divided by s0 = mean diag(S)
+  std::vector<double> dsA;                 // (ny*nx); computed when first needed
+  std::vector<double> ds_alpha, ds_beta;   // per time slice (alpha', beta')
 };
 
 bool length_supported(int n);
@@ -53,6 +58,8 @@ int validate_params(const fde_admm_params* q, std::string* msg);
 int build_setup(const fde_problem* p, const fde_admm_params* q, Setup* s, std::string* msg);
 // ADMM scalings that depend on (gamma, delta, rho) only
 void set_admm_scalings(const fde_admm_params* q, Setup* s);
+// the spatial table A(x, y) of precond_kind 2 (fills s->dsA)
+void diag_scaling_table(Setup* s);
 
 std::vector<double> grunwald_weights(double a, int n);
 std::vector<double> grunwald_weight_derivs(double a, int n);

@@ -129,6 +129,10 @@ __device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
       if (!h0) s0 = 0.0;
       if (!h1) s1 = 0.0;
       rr += s0 * s0 + s1 * s1;
+      if (a.ds_a) {
+        if (h0) s0 *= precond_scale(a, l0, i);
+        if (h1) s1 *= precond_scale(a, l1, i);
+      }
       v[e0 + k] = V{TS(s0), TS(s1)};
     }
   }
@@ -413,7 +417,11 @@ __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int i = t + T * (e0 + k);
-      const double z0 = double(v[e0 + k].x), z1 = double(v[e0 + k].y);
+      double z0 = double(v[e0 + k].x), z1 = double(v[e0 + k].y);
+      if (a.ds_a) {
+        if (h0) z0 *= precond_scale(a, l0, i);
+        if (h1) z1 *= precond_scale(a, l1, i);
+      }
       if (h0) {
         if constexpr (UPD) a.z[b0 + i] = z0 + beta * r0[k];
         else a.z[b0 + i] = z0;

@@ -21,7 +21,7 @@ FDE_EINVAL, FDE_ENOMEM, FDE_EHIP, FDE_ENONFINITE = -1, -2, -3, -4
 _STATUS = {0: "FDE_OK", 1: "FDE_ENOTCONV", -1: "FDE_EINVAL", -2: "FDE_ENOMEM", -3: "FDE_EHIP",
            -4: "FDE_ENONFINITE"}
 
-EXPORTED = ["fde_validate", "fde_host_tables", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
+EXPORTED = ["fde_validate", "fde_host_tables", "fde_host_diag_scaling", "fde_create", "fde_destroy", "fde_set_params", "fde_apply_A",
             "fde_apply_A_noalloc",
             "fde_apply_S", "fde_precond", "fde_krylov", "fde_minres", "fde_set_bounds", "fde_admm_solve", "fde_grad", "fde_time_pass",
             "fde_pass_timing", "fde_pass_stats",
@@ -80,6 +80,7 @@ def lib():
         D = ctypes.POINTER(ctypes.c_double)
         L.fde_validate.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params)]
         L.fde_host_tables.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), D, D, D, D, D, D]
+        L.fde_host_diag_scaling.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), D]
         L.fde_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Params), P, ctypes.POINTER(P)]
         L.fde_destroy.argtypes = [P]
         L.fde_set_params.argtypes = [P, ctypes.POINTER(Params)]
@@ -180,6 +181,17 @@ def host_tables(prob, prm):
     c = lambda a: a[0::2] + 1j * a[1::2]
     keys = ["psi", "hx", "hy", "ht", "a", "inv_mbar", "e_u", "k_u"]
     return dict(zip(keys, scal.tolist()), lam_x=c(lx), lam_y=c(ly), lam_t=c(lt), gx=gx, gy=gy)
+
+
+def host_diag_scaling(prob, prm):
+    """fde_host_diag_scaling: the diagonal scaling Delta of precond_kind 2, as an
+    (nt, ny, nx) array (host computation)."""
+    import numpy as np
+
+    out = np.zeros((prob.nt, prob.ny, prob.nx))
+    _check(lib().fde_host_diag_scaling(ctypes.byref(prob), ctypes.byref(prm),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), allow_notconv=False)
+    return out
 
 
 def _dptr(t, name="tensor"):

@@ -160,6 +160,8 @@ def test_batch_lockstep_small_instances():
     equals the per-instance solves bit for bit."""
     banner("batch lockstep small instances")
     ws = batchable(count=12, seed=33, maxit=4, sizes=(16, 24, 32, 48), nts=(8, 16))
+    for i in (1, 4, 7):  # the diagonally scaled preconditioner in some of them
+        ws[i] = ws[i].replace(precond_kind=2)
     a, sa, ca = run_mode(ws, "lockstep")
     b, sb, cb = run_mode(ws, "sequential")
     assert ca == cb

@@ -54,7 +54,7 @@ def test_problem_validation(field, value, frag):
 @pytest.mark.parametrize("field,value", [("gamma", 0.0), ("delta", -1.0), ("rho", 1.7), ("rho", 0.0),
                                          ("krylov_maxit", 0), ("admm_maxit", 0), ("tol_mode", 5),
                                          ("ya", 1.0), ("ua", math.nan), ("krylov_tol", -1.0),
-                                         ("precond_kind", 2), ("precond_kind", -1), ("krylov_solver", 2)])
+                                         ("precond_kind", 3), ("precond_kind", -1), ("krylov_solver", 2)])
 def test_param_validation(field, value):
     w = W.small()
     prob, prm = fde.from_workload(w)
@@ -194,3 +194,29 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(val) == want, (cname, field, int(val), want)
         seen += 1
     assert seen == sum(len(c._fields_) + 1 for c in structs.values())
+
+
+@pytest.mark.parametrize("alpha_t", [1.0, 0.6])
+def test_host_diag_scaling_matches_oracle(alpha_t):
+    """fde_host_diag_scaling (the C++ setup of precond_kind 2) against the
+    oracle's Delta = (s0 / diag S)^{1/2} from the assembled D."""
+    from oracle import admm
+    from oracle import precond as pc
+
+    w = W.small(nx=12, ny=8, nt=6).replace(obj_weights=1, alpha_t=alpha_t, precond_kind=2)
+    rng = np.random.Generator(np.random.PCG64(4))
+    w.dplus = 0.5 + rng.uniform(size=(w.ny, w.nx))
+    w.dminus = 0.3 + rng.uniform(size=(w.ny, w.nx))
+    prob, prm = fde.from_workload(w)
+    got = fde.host_diag_scaling(prob, prm)
+    d = op.disc_from(w)
+    sc = admm.scalars(w, d)
+    want = pc.scaling_factor(pc.diag_S(w, d, sc.My, sc.Mp, sc.psi))
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    # precond_kind 2 is a PCG preconditioner: MINRES with it is rejected
+    _, prm2 = fde.from_workload(w.replace(krylov_solver=1))
+    assert lib_validate(prob, prm2) == fde.FDE_EINVAL
+
+
+def lib_validate(prob, prm):
+    return fde.lib().fde_validate(ctypes.byref(prob), ctypes.byref(prm))
