@@ -351,6 +351,35 @@ def paper_tables_leg(fde, torch):
     return {"rows": rows, "paper_times": rec["time_note"]}
 
 
+def contrast_leg(fde, torch, iters):
+    """The headline grid with d+ = 1 + c sin(2 pi x), c in {0.5, 0.9, 0.99}:
+    Krylov iterations per x-step and time of `iters` ADMM iterations with S~
+    (precond_kind 0) and with the diagonally scaled S~ (precond_kind 2)."""
+    import workloads as W
+
+    rec = {"admm_iters": iters}
+    for amp in (0.5, 0.9, 0.99):
+        w = W.headline()
+        w.dplus = W.coef_sine_x(w.nx, w.ny, amp=amp)
+        yh = torch.from_numpy(w.yhat).to("cuda")
+        row = {}
+        for tag, kind in (("S~", 0), ("S~diag", 2)):
+            prob, prm = fde.from_workload(w.replace(precond_kind=kind), admm_tol=0.0, admm_maxit=iters)
+            with fde.Context(prob, prm) as c:
+                c.autotune()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st, _ = c.admm_solve(yh)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+            row[tag] = {"pcg_avg": round(st["pcg_total"] / st["admm_iters"], 2), "s": round(t, 3),
+                        "pcg_iters_per_s": round(st["pcg_total"] / t, 1)}
+        row["krylov_ratio"] = round(row["S~diag"]["pcg_avg"] / row["S~"]["pcg_avg"], 3)
+        row["time_ratio"] = round(row["S~diag"]["s"] / row["S~"]["s"], 3)
+        rec[f"c={amp}"] = row
+    return rec
+
+
 def batch_modes(fde, torch, ws, cap, modes):
     """Time fde_batch_solve over the instances ws (each run for `cap` ADMM
     iterations) in each (tag, fp32, mode) of `modes`."""
@@ -516,7 +545,8 @@ def main():
         var = {}
         # (the headline's J1 = I, so Algorithm 2 takes c_y = 1.5, c_u = 10 gamma: R_y, R_u nonzero)
         alg2 = dict(prox=1, prox_cy=1.5, prox_cu=10 * w.gamma)
-        for tag, kw in (("S~_alg1", {}), ("S^_alg1", dict(precond_kind=1)), ("S~_alg2", alg2),
+        for tag, kw in (("S~_alg1", {}), ("S^_alg1", dict(precond_kind=1)), ("S~diag_alg1", dict(precond_kind=2)),
+                        ("S~_alg2", alg2),
                         ("S^_alg2", dict(alg2, precond_kind=1)), ("minres_K~_alg1", dict(krylov_solver=1))):
             prob, prm = fde.from_workload(w.replace(**kw), admm_tol=0.0, admm_maxit=a.variant_iters)
             with fde.Context(prob, prm) as c3:
@@ -529,6 +559,8 @@ def main():
             var[tag] = {"admm_iters": st3["admm_iters"], "pcg_avg": round(st3["pcg_total"] / st3["admm_iters"], 2),
                         "s": round(t, 3), "residuals": [st3["r_p"], st3["r_y"], st3["r_u"]]}
         out["variants_headline"] = var
+        progress("coefficient contrast: S~ against the diagonally scaled S~")
+        out["contrast_headline"] = contrast_leg(fde, torch, a.variant_iters)
 
     # ---- precision form: 1024^2 x 32, FP32 preconditioner against FP64 ----------
     if not a.no_full:
