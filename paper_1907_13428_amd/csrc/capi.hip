@@ -118,10 +118,11 @@ struct fde_ctx {
   bool ycol = false;  // coefficient fields constant along y: per-column y-pass multipliers
   double *dplus = nullptr, *dminus = nullptr;
   double *invMp = nullptr, *My = nullptr, *Mu = nullptr, *Mp = nullptr, *wts = nullptr, *ones = nullptr;
-  // precond_kind 2: the table A(x, y) and per-slice (alpha', beta') of the diagonal
-  // scaling (allocated when that kind is first used)
-  double* dsA = nullptr;
-  double2* dsab = nullptr;
+  // precond_kind 2: the tables of the diagonal scaling and each slice's table
+  // (allocated when that kind is first used, regrown when it needs more tables)
+  double* ds_tab = nullptr;
+  int* ds_class = nullptr;
+  size_t ds_tab_n = 0;
   double2 *dxA = nullptr, *dxB = nullptr, *dyA = nullptr, *dyB = nullptr;  // dL/dalpha, dL/dbeta
 
   // workspace fields
@@ -363,8 +364,8 @@ fde::PrecondArgs pre_args(fde_ctx* c, double* r, double* z) {
   a.tile_y = c->tile_pre_y;
   a.tile_t = c->tile_pre_t;
   if (c->prm.precond_kind == 2) {
-    a.ds_a = c->dsA;
-    a.ds_ab = c->dsab;
+    a.ds_tab = c->ds_tab;
+    a.ds_class = c->ds_class;
   }
   return a;
 }
@@ -1073,14 +1074,14 @@ fde_status upload_admm_tables(fde_ctx* c) {
   HIP_TRY(hipMemcpy(c->Mp, s.Mp.data(), bytes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->wts, s.wts.data(), bytes, hipMemcpyHostToDevice));
   if (c->prm.precond_kind == 2) {
-    if (!c->dsA) {
-      HIP_TRY(c->alloc(&c->dsA, s.dsA.size()));
-      HIP_TRY(hipMemcpy(c->dsA, s.dsA.data(), sizeof(double) * s.dsA.size(), hipMemcpyHostToDevice));
-      HIP_TRY(c->alloc(&c->dsab, (size_t)c->nt));
+    if (s.ds_tab.size() > c->ds_tab_n) {
+      // (a superseded smaller table stays in the context's allocations until it is destroyed)
+      HIP_TRY(c->alloc(&c->ds_tab, s.ds_tab.size()));
+      c->ds_tab_n = s.ds_tab.size();
     }
-    std::vector<double2> ab(c->nt);
-    for (int t = 0; t < c->nt; ++t) ab[t] = double2{s.ds_alpha[t], s.ds_beta[t]};
-    HIP_TRY(hipMemcpy(c->dsab, ab.data(), sizeof(double2) * ab.size(), hipMemcpyHostToDevice));
+    if (!c->ds_class) HIP_TRY(c->alloc(&c->ds_class, (size_t)c->nt));
+    HIP_TRY(hipMemcpy(c->ds_tab, s.ds_tab.data(), sizeof(double) * s.ds_tab.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->ds_class, s.ds_class.data(), sizeof(int) * s.ds_class.size(), hipMemcpyHostToDevice));
   }
   return FDE_OK;
 }
@@ -1136,8 +1137,8 @@ struct SliceOps {
     a.psi = 1.0;
     a.inv_n = 1.0 / (double)plane;
     a.div_mode = 1;
-    a.ds_a = nullptr;  // the transposed slice operator's own circulant, no scaling of S
-    a.ds_ab = nullptr;
+    a.ds_tab = nullptr;  // the transposed slice operator's own circulant, no scaling of S
+    a.ds_class = nullptr;
     return fde::launch_precond(a, c->fp32, c->stream, nullptr, nullptr);
   }
   hipError_t dots(int count, const double* const* a, const double* const* b) {
@@ -1469,7 +1470,7 @@ fde_status fde_host_diag_scaling(const fde_problem* prob, const fde_admm_params*
   const size_t plane = (size_t)s.nx * s.ny;
   for (int t = 0; t < s.nt; ++t)
     for (size_t k = 0; k < plane; ++k)
-      delta[(size_t)t * plane + k] = 1.0 / std::sqrt(s.ds_alpha[t] + s.ds_beta[t] * s.dsA[k]);
+      delta[(size_t)t * plane + k] = s.ds_tab[(size_t)s.ds_class[t] * plane + k];
   return FDE_OK;
 }
 

@@ -137,16 +137,18 @@ struct PrecondArgs {
   int pdir;             // x-inverse output into z: 0 the preconditioned residual; 1 p = z + beta p
                         // (z is the direction p, updated in place); 2 p = z (the first direction)
   // diagonal scaling Delta S~^{-1} Delta (nullptr: none): Delta at node (x, y, t) is
-  // (ab[t].x + ab[t].y A[y][x])^{-1/2}; the x-forward pass scales its FFT input, the
-  // x-inverse pass its output
-  const double* ds_a;   // (ny, nx)
-  const double2* ds_ab; // per time slice
+  // ds_tab[ds_class[t]][y][x]; the x-forward pass scales its FFT input, the x-inverse
+  // pass its output
+  const double* ds_tab;  // (classes, ny, nx)
+  const int* ds_class;   // per time slice
 };
 
-// the diagonal scaling of the preconditioner at element i of x-line l (t = l / ny, y = l % ny)
-__device__ __forceinline__ double precond_scale(const PrecondArgs& a, int l, int i) {
-  const double2 ab = a.ds_ab[l / a.ny];
-  return 1.0 / sqrt(ab.x + ab.y * a.ds_a[(size_t)(l % a.ny) * a.nx + i]);
+// the row of the preconditioner's diagonal scaling for x-line l (t = l / ny, y = l % ny),
+// nullptr without scaling; l must be a line of the field
+__device__ __forceinline__ const double* precond_scale_row(const PrecondArgs& a, int l) {
+  if (!a.ds_tab) return nullptr;
+  const int t = l / a.ny;
+  return a.ds_tab + ((size_t)a.ds_class[t] * a.ny + (l - t * a.ny)) * a.nx;
 }
 
 // ---------------------------------------------------------------------------
@@ -238,8 +240,8 @@ __device__ __forceinline__ PrecondArgs batch_local(const PrecondArgs& s) {
   a.scal_w = as_global(a.scal_w);
   a.ints = as_global(a.ints);
   a.rzs_partial = as_global(a.rzs_partial);
-  a.ds_a = as_global(a.ds_a);
-  a.ds_ab = as_global(a.ds_ab);
+  a.ds_tab = as_global(a.ds_tab);
+  a.ds_class = as_global(a.ds_class);
   return a;
 }
 

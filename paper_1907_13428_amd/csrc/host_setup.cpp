@@ -293,6 +293,8 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
   // diag(S) = My(t) + psi^2 (sum_{t'>t} ct[t'-t]^2 / Mp(t') + A(x, y) / Mp(t))
   s->ds_alpha.clear();
   s->ds_beta.clear();
+  s->ds_class.clear();
+  s->ds_tab.clear();
   if (q->precond_kind == 2) {
     if (s->dsA.empty()) diag_scaling_table(s);
     const double psi2 = s->psi * s->psi;
@@ -314,6 +316,23 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
       s->ds_alpha[t] = (double)(s->ds_alpha[t] / s0);
       s->ds_beta[t] = (double)(s->ds_beta[t] / s0);
     }
+    // one table of Delta per distinct (alpha', beta'): implicit Euler has at most
+    // three (interior levels, the last two), a fractional time order one per level
+    const size_t plane = s->dsA.size();
+    s->ds_class.assign(nt, 0);
+    std::vector<int> first;  // a slice of each class
+    for (int t = 0; t < nt; ++t) {
+      int c = 0;
+      while (c < (int)first.size() &&
+             !(s->ds_alpha[first[c]] == s->ds_alpha[t] && s->ds_beta[first[c]] == s->ds_beta[t]))
+        ++c;
+      if (c == (int)first.size()) first.push_back(t);
+      s->ds_class[t] = c;
+    }
+    s->ds_tab.resize(first.size() * plane);
+    for (size_t c = 0; c < first.size(); ++c)
+      for (size_t k = 0; k < plane; ++k)
+        s->ds_tab[c * plane + k] = 1.0 / std::sqrt(s->ds_alpha[first[c]] + s->ds_beta[first[c]] * s->dsA[k]);
   }
 }
 

@@ -46,9 +46,12 @@ struct Setup {
   std::vector<double> dplus, dminus;   // (ny*nx) copies when var
   // precond_kind 2: diag(S) = alpha_t + beta_t A(x, y) (eq. (3.9) in the psi-scaled
   // form), A the spatial part of the squared column norms of D; the kernels scale
-  // by Delta = (alpha'_t + beta'_t A)^{-1/2}, primes: divided by s0 = mean diag(S)
+  // by Delta = (alpha'_t + beta'_t A)^{-1/2}, primes: divided by s0 = mean diag(S).
+  // Slices with equal (alpha', beta') share one table of Delta (a class).
   std::vector<double> dsA;                 // (ny*nx); computed when first needed
   std::vector<double> ds_alpha, ds_beta;   // per time slice (alpha', beta')
+  std::vector<int> ds_class;               // per time slice: its table
+  std::vector<double> ds_tab;              // (classes, ny*nx): Delta
 };
 
 bool length_supported(int n);

@@ -47,7 +47,7 @@ constexpr int pre_x_groups(int T) { return kPreThreads / T + (kPreThreads % T ? 
 // ---------------------------------------------------------------------------
 // pass 1: x-direction real-to-complex
 // ---------------------------------------------------------------------------
-template <int L, typename TS, bool FUSE>
+template <int L, typename TS, bool FUSE, bool SC>
 __device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
   using V = cplx<TS>;
   constexpr int E = default_E(L);
@@ -71,13 +71,20 @@ __device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
   // is formed, so that its HBM latency overlaps the ordered sum of partials.
   constexpr int G = (E % 4 == 0) ? 4 : (E % 2 == 0 ? 2 : 1);
   const size_t b0 = h0 ? (size_t)l0 * L : 0, b1 = h1 ? (size_t)l1 * L : 0;
-  double r0[G], r1[G], q0[G], q1[G], x0[G], x1[G], p0[G], p1[G];
+  // diagonal scaling rows (a missing line reads line 0's and is zeroed)
+  const double* ds0 = SC ? precond_scale_row(a, h0 ? l0 : 0) : nullptr;
+  const double* ds1 = SC ? precond_scale_row(a, h1 ? l1 : 0) : nullptr;
+  double r0[G], r1[G], q0[G], q1[G], x0[G], x1[G], p0[G], p1[G], d0[G], d1[G];
   auto load_group = [&](int e0) {
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int i = t + T * (e0 + k);
       r0[k] = a.r[b0 + i];
       r1[k] = a.r[b1 + i];
+      if constexpr (SC) {
+        d0[k] = ds0[i];
+        d1[k] = ds1[i];
+      }
       if constexpr (FUSE) {
         q0[k] = a.q[b0 + i];
         q1[k] = a.q[b1 + i];
@@ -129,9 +136,9 @@ __device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
       if (!h0) s0 = 0.0;
       if (!h1) s1 = 0.0;
       rr += s0 * s0 + s1 * s1;
-      if (a.ds_a) {
-        if (h0) s0 *= precond_scale(a, l0, i);
-        if (h1) s1 *= precond_scale(a, l1, i);
+      if constexpr (SC) {
+        s0 *= d0[k];
+        s1 *= d1[k];
       }
       v[e0 + k] = V{TS(s0), TS(s1)};
     }
@@ -162,16 +169,16 @@ __device__ __forceinline__ void pre_xfwd_body(const PrecondArgs& a, int bid) {
   }
 }
 
-template <int L, typename TS, bool FUSE>
+template <int L, typename TS, bool FUSE, bool SC>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd(PrecondArgs a) {
-  pre_xfwd_body<L, TS, FUSE>(a, blockIdx.x);
+  pre_xfwd_body<L, TS, FUSE, SC>(a, blockIdx.x);
 }
 
 // the batched twin: many instances in one launch (BatchArgs)
-template <int L, typename TS, bool FUSE>
+template <int L, typename TS, bool FUSE, bool SC>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xfwd_b(BatchArgs<PrecondArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  pre_xfwd_body<L, TS, FUSE>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
+  pre_xfwd_body<L, TS, FUSE, SC>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +367,7 @@ __global__ __launch_bounds__((CCfg<L, S>::NT)) void k_pre_cc_b(BatchArgs<Precond
 // pass 5: half spectrum -> real lines.  OUT 0: z; 1: z and partial sums of
 // (r, z); 2: the PCG direction p = z + beta p, in place in a.z
 // ---------------------------------------------------------------------------
-template <int L, typename TS, int OUT>
+template <int L, typename TS, int OUT, bool SC>
 __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
   constexpr bool DOT = OUT == 1, UPD = OUT == 2;
   using V = cplx<TS>;
@@ -378,6 +385,9 @@ __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
   LineLds<V> buf{lds + g * lpad_size(L), 1};
   const V* tw = reinterpret_cast<const V*>(a.twx);
   const V* spec = reinterpret_cast<const V*>(a.spec);
+  // diagonal scaling rows (a missing line reads line 0's; nothing of it is stored)
+  const double* ds0 = SC ? precond_scale_row(a, h0 ? l0 : 0) : nullptr;
+  const double* ds1 = SC ? precond_scale_row(a, h1 ? l1 : 0) : nullptr;
 
   V v[E];
 #pragma unroll
@@ -405,7 +415,7 @@ __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
   double rz = 0.0;
 #pragma unroll
   for (int e0 = 0; e0 < E; e0 += G) {
-    double r0[G], r1[G];
+    double r0[G], r1[G], d0[G], d1[G];
     if constexpr (DOT || UPD) {
 #pragma unroll
       for (int k = 0; k < G; ++k) {
@@ -414,13 +424,21 @@ __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
         r1[k] = opnd[b1 + i];
       }
     }
+    if constexpr (SC) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int i = t + T * (e0 + k);
+        d0[k] = ds0[i];
+        d1[k] = ds1[i];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       const int i = t + T * (e0 + k);
       double z0 = double(v[e0 + k].x), z1 = double(v[e0 + k].y);
-      if (a.ds_a) {
-        if (h0) z0 *= precond_scale(a, l0, i);
-        if (h1) z1 *= precond_scale(a, l1, i);
+      if constexpr (SC) {
+        z0 *= d0[k];
+        z1 *= d1[k];
       }
       if (h0) {
         if constexpr (UPD) a.z[b0 + i] = z0 + beta * r0[k];
@@ -440,16 +458,16 @@ __device__ __forceinline__ void pre_xinv_body(const PrecondArgs& a, int bid) {
   }
 }
 
-template <int L, typename TS, int OUT>
+template <int L, typename TS, int OUT, bool SC>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xinv(PrecondArgs a) {
-  pre_xinv_body<L, TS, OUT>(a, blockIdx.x);
+  pre_xinv_body<L, TS, OUT, SC>(a, blockIdx.x);
 }
 
 // the batched twin
-template <int L, typename TS, int OUT>
+template <int L, typename TS, int OUT, bool SC>
 __global__ __launch_bounds__(kPreThreads) void k_pre_xinv_b(BatchArgs<PrecondArgs> b) {
   const int i = batch_instance(b, blockIdx.x);
-  pre_xinv_body<L, TS, OUT>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
+  pre_xinv_body<L, TS, OUT, SC>(batch_local(b.args[i]), blockIdx.x - b.first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,12 +480,12 @@ constexpr bool batch_dim(int n) {
          n == 256 || n == 384 || n == 512;
 }
 using PreBatchKernel = void (*)(BatchArgs<PrecondArgs>);
-template <int L, typename TS, bool FUSE> static PreBatchKernel xfwd_twin() {
-  if constexpr (batch_dim(L) && FUSE) return k_pre_xfwd_b<L, TS, FUSE>;
+template <int L, typename TS, bool FUSE, bool SC> static PreBatchKernel xfwd_twin() {
+  if constexpr (batch_dim(L) && FUSE) return k_pre_xfwd_b<L, TS, FUSE, SC>;
   else return nullptr;
 }
-template <int L, typename TS, int OUT> static PreBatchKernel xinv_twin() {
-  if constexpr (batch_dim(L) && OUT == 2) return k_pre_xinv_b<L, TS, OUT>;
+template <int L, typename TS, int OUT, bool SC> static PreBatchKernel xinv_twin() {
+  if constexpr (batch_dim(L) && OUT == 2) return k_pre_xinv_b<L, TS, OUT, SC>;
   else return nullptr;
 }
 template <int L, typename TS, int MODE, int SIGN, int S> static PreBatchKernel cc_twin() {
@@ -479,20 +497,27 @@ template <int L, typename TS, int MODE, int SIGN, int S> static PreBatchKernel c
   X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(50) X(64) X(80) X(96) X(100) X(128) X(160) X(192) X(256) \
   X(384) X(512) X(768) X(1024)
 
+// SC: the diagonal scaling Delta S~^{-1} Delta (a.ds_tab set)
+template <int L, typename TS, bool SC>
+static void pre_x_sc(const PrecondArgs& a, bool fwd, int blocks, hipStream_t s) {
+  if (fwd) {
+    if (a.q) launch_pass(k_pre_xfwd<L, TS, true, SC>, xfwd_twin<L, TS, true, SC>(), blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xfwd<L, TS, false, SC>, xfwd_twin<L, TS, false, SC>(), blocks, kPreThreads, s, a);
+  } else {
+    if (a.pdir == 1) launch_pass(k_pre_xinv<L, TS, 2, SC>, xinv_twin<L, TS, 2, SC>(), blocks, kPreThreads, s, a);
+    else if (a.partial2) launch_pass(k_pre_xinv<L, TS, 1, SC>, xinv_twin<L, TS, 1, SC>(), blocks, kPreThreads, s, a);
+    else launch_pass(k_pre_xinv<L, TS, 0, SC>, xinv_twin<L, TS, 0, SC>(), blocks, kPreThreads, s, a);
+  }
+}
+
 template <int L, typename TS>
 static hipError_t pre_x(const PrecondArgs& a, bool fwd, hipStream_t s, int* nb) {
   constexpr int LPB = kPreThreads / (L / default_E(L));
   const int pairs = (a.ny * a.nt + 1) / 2;
   const int blocks = (pairs + LPB - 1) / LPB;
   if (nb) *nb = blocks;
-  if (fwd) {
-    if (a.q) launch_pass(k_pre_xfwd<L, TS, true>, xfwd_twin<L, TS, true>(), blocks, kPreThreads, s, a);
-    else launch_pass(k_pre_xfwd<L, TS, false>, xfwd_twin<L, TS, false>(), blocks, kPreThreads, s, a);
-  } else {
-    if (a.pdir == 1) launch_pass(k_pre_xinv<L, TS, 2>, xinv_twin<L, TS, 2>(), blocks, kPreThreads, s, a);
-    else if (a.partial2) launch_pass(k_pre_xinv<L, TS, 1>, xinv_twin<L, TS, 1>(), blocks, kPreThreads, s, a);
-    else launch_pass(k_pre_xinv<L, TS, 0>, xinv_twin<L, TS, 0>(), blocks, kPreThreads, s, a);
-  }
+  if (a.ds_tab) pre_x_sc<L, TS, true>(a, fwd, blocks, s);
+  else pre_x_sc<L, TS, false>(a, fwd, blocks, s);
   return hipGetLastError();
 }
 
