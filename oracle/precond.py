@@ -16,8 +16,8 @@ is a circulant too, with eigenvalues |Lambda + sqrt(a mbar_p)|^2 / mbar_p
 (precond_kind = 1).
 Variable coefficients (the remark closing Sec. 4: circulants lose effect when
 the coefficients vary, and a diagonal-times-structured form is the remedy the
-paper points to) -- precond_kind = 2, this build's reading: the symmetric
-diagonal scaling of S~,
+paper points to) -- precond_kind = 2, read here as the symmetric diagonal
+scaling of S~,
     P^{-1} = Delta S~^{-1} Delta,  Delta = (s0 / diag(S))^{1/2},
 with diag(S) the exact diagonal of S = M_y + B^T M_p^{-1} B (eq. (3.9)) and s0
 its mean over the grid (any constant gives the same PCG iterates).  Delta
