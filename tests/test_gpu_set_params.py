@@ -1,5 +1,6 @@
 """fde_set_params on a live context: the new ADMM settings (gamma, delta, rho,
-Algorithm 2, the matching preconditioner of eq. (3.11)) must reach every
+Algorithm 2, the matching preconditioner of eq. (3.11), the diagonally scaled
+S~ of variable coefficients) must reach every
 kernel of the next solve, including the PCG iterations replayed from the
 captured graph, whose launches hold the preconditioner's scalars by value.
 
@@ -27,6 +28,7 @@ CHANGES = {
     "rho_gamma_delta": dict(rho=1.5, gamma=1e-3, delta=0.4),
     "matching_precond": dict(precond_kind=1),
     "alg2": dict(prox=1, rho=0.8, prox_cy=1.5, prox_cu=2e-6),
+    "scaled_precond": dict(precond_kind=2, rho=1.2),
 }
 
 
@@ -60,8 +62,12 @@ def test_set_params_krylov_uses_new_preconditioner(name):
     d = op.disc_from(w1)
     sc = admm.scalars(w1, d)
     tab = pc.precond_tables(w1, d)
-    xr, itr, _, ok = admm.pcg(lambda v: admm.apply_S(d, sc, v), lambda v: pc.apply_precond(tab, v), b, x0,
-                              w1.krylov_tol, w1.krylov_maxit)
+    if w1.precond_kind == 2:
+        delta = pc.scaling_factor(pc.diag_S(w1, d, sc.My, sc.Mp, sc.psi))
+        M = lambda v: pc.apply_precond_scaled(tab, delta, v)
+    else:
+        M = lambda v: pc.apply_precond(tab, v)
+    xr, itr, _, ok = admm.pcg(lambda v: admm.apply_S(d, sc, v), M, b, x0, w1.krylov_tol, w1.krylov_maxit)
     assert ok and abs(it - itr) <= 1, (it, itr)
     assert relres <= w1.krylov_tol
     assert rel(got, xr) <= 1e-9, rel(got, xr)
