@@ -1,6 +1,10 @@
 // Host-side setup (see host_setup.hpp).
 #include "host_setup.hpp"
 
+#include <algorithm>
+#include <functional>
+#include <thread>
+
 #include <cmath>
 #include <cstdio>
 
@@ -336,44 +340,75 @@ void set_admm_scalings(const fde_admm_params* q, Setup* s) {
   }
 }
 
+namespace {
+// Diagonal and squared off-diagonal column sums of one line operator
+// L = c (diag(cp) G + diag(cm) G^T), G[r, i] = g_{r-i+1} (zero for r < i-1):
+// column i holds c (cp[r] g_{r-i+1} + cm[r] g_{i-r+1}) in row r, the first
+// term only for r >= i-1, the second only for r <= i+1.  Adds L_ii to dia[i]
+// and sum_{r != i} L[r, i]^2 to off[i] (stride `st` between the line's nodes).
+void line_column_sums(const AxisTables& ax, const double* cp, const double* cm, int n, double* dia, double* off,
+                      size_t st) {
+  const std::vector<double>& g = ax.g;
+  std::vector<double> g2(n + 2, 0.0), cp2(n), cm2(n);
+  for (int k = 0; k <= n && k < (int)g.size(); ++k) g2[k] = g[k] * g[k];
+  for (int r = 0; r < n; ++r) {
+    cp2[r] = cp[r] * cp[r];
+    cm2[r] = cm[r] * cm[r];
+  }
+  const double c2 = ax.c * ax.c;
+  for (int i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int r = i + 2; r < n; ++r) acc += cp2[r] * g2[r - i + 1];  // below the band: G only
+    for (int r = 0; r <= i - 2; ++r) acc += cm2[r] * g2[i - r + 1];  // above it: G^T only
+    if (i >= 1) {
+      const double v = cp[i - 1] * g[0] + cm[i - 1] * g[2];
+      acc += v * v;
+    }
+    if (i + 1 < n) {
+      const double v = cp[i + 1] * g[2] + cm[i + 1] * g[0];
+      acc += v * v;
+    }
+    dia[i * st] += ax.c * (cp[i] + cm[i]) * g[1];
+    off[i * st] += c2 * acc;
+  }
+}
+}  // namespace
+
 void diag_scaling_table(Setup* s) {
   // A(x, y) = (ct[0] - Lx_ii - Ly_ii)^2 + sum_{r != i} Lx[r, i]^2 + sum_{r != i} Ly[r, i]^2,
   // with Lx[r, i] = cx (d+(r) G[r, i] + d-(r) G[i, r]) along the x-line of the node
-  // (eq. (4.6)-(4.7); G[r, i] = g_{r-i+1} for r >= i-1) and Ly the same along y
+  // (eq. (4.6)-(4.7)) and Ly the same along y; lines split over host threads
   const int nx = s->nx, ny = s->ny;
-  auto dp = [&](int i, int j) { return s->var ? s->dplus[(size_t)j * nx + i] : 1.0; };
-  auto dm = [&](int i, int j) { return s->var ? s->dminus[(size_t)j * nx + i] : 1.0; };
-  // entry (r, i) of a line operator: coefficients at row r
-  auto entry = [](const AxisTables& ax, int r, int i, double cp, double cm) {
-    const int a = r - i + 1, b = i - r + 1;
-    const double gr = a >= 0 ? ax.g[a] : 0.0, gi = b >= 0 ? ax.g[b] : 0.0;
-    return ax.c * (cp * gr + cm * gi);
+  const size_t plane = (size_t)nx * ny;
+  std::vector<double> ones((size_t)std::max(nx, ny), 1.0);
+  std::vector<double> off(plane, 0.0), dia(plane, 0.0), offy(plane, 0.0), diay(plane, 0.0);
+  const int nthr = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto run = [&](int count, const std::function<void(int)>& f) {
+    std::vector<std::thread> th;
+    for (int w = 0; w < nthr; ++w)
+      th.emplace_back([&, w]() {
+        for (int k = w; k < count; k += nthr) f(k);
+      });
+    for (auto& t : th) t.join();
   };
-  std::vector<double> off((size_t)nx * ny, 0.0), dia((size_t)nx * ny, 0.0);
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) {
-      long double acc = 0;
-      for (int r = 0; r < nx; ++r) {
-        const double v = entry(s->x, r, i, dp(r, j), dm(r, j));
-        if (r == i) dia[(size_t)j * nx + i] += v;
-        else acc += (long double)v * v;
+  run(ny, [&](int j) {  // x-lines: contiguous coefficients of row j
+    const double* cp = s->var ? &s->dplus[(size_t)j * nx] : ones.data();
+    const double* cm = s->var ? &s->dminus[(size_t)j * nx] : ones.data();
+    line_column_sums(s->x, cp, cm, nx, &dia[(size_t)j * nx], &off[(size_t)j * nx], 1);
+  });
+  run(nx, [&](int i) {  // y-lines: column i of the coefficient fields
+    std::vector<double> cp(ny, 1.0), cm(ny, 1.0);
+    if (s->var)
+      for (int j = 0; j < ny; ++j) {
+        cp[j] = s->dplus[(size_t)j * nx + i];
+        cm[j] = s->dminus[(size_t)j * nx + i];
       }
-      off[(size_t)j * nx + i] += (double)acc;
-    }
-  for (int i = 0; i < nx; ++i)
-    for (int j = 0; j < ny; ++j) {
-      long double acc = 0;
-      for (int r = 0; r < ny; ++r) {
-        const double v = entry(s->y, r, j, dp(i, r), dm(i, r));
-        if (r == j) dia[(size_t)j * nx + i] += v;
-        else acc += (long double)v * v;
-      }
-      off[(size_t)j * nx + i] += (double)acc;
-    }
-  s->dsA.resize((size_t)nx * ny);
-  for (size_t k = 0; k < s->dsA.size(); ++k) {
-    const double d0 = s->ct[0] - dia[k];
-    s->dsA[k] = d0 * d0 + off[k];
+    line_column_sums(s->y, cp.data(), cm.data(), ny, &diay[i], &offy[i], (size_t)nx);
+  });
+  s->dsA.resize(plane);
+  for (size_t k = 0; k < plane; ++k) {
+    const double d0 = s->ct[0] - dia[k] - diay[k];
+    s->dsA[k] = d0 * d0 + off[k] + offy[k];
   }
 }
 
