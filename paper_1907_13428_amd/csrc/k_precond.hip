@@ -194,7 +194,9 @@ template <int L, int S = 0> struct CCfg {
   static constexpr int Pmax = cap(cap(16, kPreThreads / T), (131072 / (lpad_size(L) * 16)) - 1);
   static constexpr int P = (Pmax >> S) > 0 ? (Pmax >> S) : 1;
   static constexpr int NT = ((P * T + 63) / 64) * 64;
-  static constexpr int RS = P + 1;
+  // LDS row stride: a spare column for the threads beyond P*T; dropped for
+  // columns of 1024 points and more when no thread needs it (as in the y-pass)
+  static constexpr int RS = (L >= 1024 && (P * T) % 64 == 0) ? P : P + 1;
   static_assert(Pmax >= 1, "tile");
 };
 
