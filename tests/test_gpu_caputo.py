@@ -35,11 +35,13 @@ def case(kind):
         return W.small(nx=16, ny=24, nt=50).replace(alpha_t=0.7)
     if kind == "radix5_nt80_0.4":
         return W.small(nx=12, ny=8, nt=80).replace(alpha_t=0.4)
+    if kind == "long_t_512_0.6":  # the time embedding is 1024 points long
+        return W.small(nx=8, ny=6, nt=512).replace(alpha_t=0.6)
     raise KeyError(kind)
 
 
 CASES = ["small_0.7", "var_ragged_0.3", "radix3_nt12_0.5", "long_t_64", "nt4_0.1", "radix5_nt50_0.7",
-         "radix5_nt80_0.4"]
+         "radix5_nt80_0.4", "long_t_512_0.6"]
 
 
 @pytest.mark.parametrize("kind", CASES)

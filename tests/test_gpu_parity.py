@@ -57,12 +57,20 @@ def make(kind):
         return W.small(nx=160, ny=100, nt=50).replace(alpha=1.8, beta=1.2)
     if kind == "radix5_colcoef_100x50x8":
         return W.headline(nx=100, ny=50, nt=8)
+    # columns of 1024 points and more: tiles without the spare LDS column
+    if kind == "tall_var_8x768x4":  # 1536-point operator columns
+        return var_fields(W.small(nx=8, ny=768, nt=4).replace(alpha=1.6, beta=1.3))
+    if kind == "tall_6x512x6":  # 1024-point operator columns
+        return W.small(nx=6, ny=512, nt=6).replace(alpha=1.25, beta=1.75)
+    if kind == "deep_4x6x1024":  # 1024-point preconditioner columns along t
+        return W.small(nx=4, ny=6, nt=1024)
     raise KeyError(kind)
 
 
 OP_CASES = ["small", "headline_24x16x8", "ragged_var_24x48x6", "const_96x12x4", "tiny_var_6x8x4",
             "laplace_48x24x6", "radix3_192x96x12", "long_1024x8x4", "tall_8x1024x4", "min_4x4x4",
-            "min_mixed_4x6x12", "radix5_var_50x80x100", "radix5_160x100x50", "radix5_colcoef_100x50x8"]
+            "min_mixed_4x6x12", "radix5_var_50x80x100", "radix5_160x100x50", "radix5_colcoef_100x50x8",
+            "tall_var_8x768x4", "tall_6x512x6", "deep_4x6x1024"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -439,7 +447,8 @@ def test_graph_replays_match_eager_launches(monkeypatch):
 
 
 @pytest.mark.parametrize("tiles", ["1,1,1", "2,2,2", "0,2,1"])
-@pytest.mark.parametrize("kind", ["headline_24x16x8", "radix3_192x96x12", "long_1024x8x4"])
+@pytest.mark.parametrize("kind", ["headline_24x16x8", "radix3_192x96x12", "long_1024x8x4", "tall_var_8x768x4",
+                                  "tall_6x512x6", "deep_4x6x1024"])
 def test_tile_variants_match_oracle(monkeypatch, tiles, kind):
     """Every column-tile variant the autotuner may pick gives the oracle's results."""
     banner("tiles", tiles, kind)
