@@ -58,7 +58,7 @@ def parse():
                     help="only sweep the ADMM settings (psi scaling of the u copies, delta, rho) on the headline "
                          "grid: iterations and time to the 1e-4 and 1e-6 stopping tests; prints one JSON line")
     ap.add_argument("--sweep-cap", type=int, default=3000, help="ADMM iteration cap per setting of --admm-sweep")
-    ap.add_argument("--passes-only", choices=["headline", "precision", "precision_fp32"],
+    ap.add_argument("--passes-only", choices=["headline", "headline_fp32", "precision", "precision_fp32"],
                     help="only the in-solve per-pass timing on that grid (warmup W, then K timed ADMM "
                          "iterations); prints one JSON line (for kernel traces and counters)")
     return ap.parse_args()
@@ -173,11 +173,11 @@ def in_solve_passes(ctx, yhat, state, torch):
 def passes_only_leg(fde, torch, grid, warmup, steps):
     """The in-solve per-pass table alone: `warmup` ADMM iterations from zero,
     then `steps` more with pass timing, on the headline grid or the 1024^2 x 32
-    precision form (FP64, or with the FP32 preconditioner)."""
+    precision form, each in FP64 or with the FP32 preconditioner."""
     import workloads as W
 
-    w = W.headline() if grid == "headline" else W.precision()
-    fp32 = 1 if grid == "precision_fp32" else 0
+    w = W.headline() if grid.startswith("headline") else W.precision()
+    fp32 = 1 if grid.endswith("_fp32") else 0
     yhat = torch.from_numpy(w.yhat).to("cuda")
     prob, prm = fde.from_workload(w, precond_fp32=fp32, admm_tol=0.0, admm_maxit=max(warmup, 1))
     with fde.Context(prob, prm) as ctx:
