@@ -1,6 +1,7 @@
 // Drives the host-side setup (validation, Grünwald weights, embedding and
-// T. Chan tables, twiddles, ADMM scalings) over the supported size range and
-// the parameter variants, for a build under AddressSanitizer and
+// T. Chan tables, twiddles, ADMM scalings, the threaded diagonal-scaling
+// tables) over the supported size range and the parameter variants, for a
+// build under AddressSanitizer and
 // UndefinedBehaviorSanitizer.  Exit status 0 when every table is finite and
 // every invalid input is rejected.
 #include <cmath>
@@ -76,6 +77,19 @@ void run(const fde_problem& p, const fde_admm_params& q, const std::string& tag)
   check(finite_all(s.tchan_t) && finite_all(s.tw_t) && finite_all(s.ct), tag + ": time tables");
   check(finite_all(s.My) && finite_all(s.Mu) && finite_all(s.Mp) && finite_all(s.invMp), tag + ": scalings");
   check(std::isfinite(s.psi) && s.psi > 0 && std::isfinite(s.a) && std::isfinite(s.inv_mbar), tag + ": scalars");
+  if (q.precond_kind == 2) {
+    // diagonal scaling: one positive table per class, every time slice in a class
+    const size_t plane = (size_t)p.nx * p.ny;
+    check(s.dsA.size() == plane && finite_all(s.dsA), tag + ": diag(S) spatial table");
+    check(s.ds_class.size() == (size_t)p.nt && !s.ds_tab.empty() && s.ds_tab.size() % plane == 0,
+          tag + ": scaling table sizes");
+    const int classes = (int)(s.ds_tab.size() / plane);
+    bool in_range = true, positive = true;
+    for (int c : s.ds_class) in_range = in_range && c >= 0 && c < classes;
+    for (double v : s.ds_tab) positive = positive && std::isfinite(v) && v > 0;
+    check(in_range, tag + ": scaling classes");
+    check(positive, tag + ": scaling table positive");
+  }
 }
 }  // namespace
 
@@ -106,6 +120,22 @@ int main() {
     p.psi_scaling = 2;
     p.obj_weights = 1;
     run(p, q, "psi scaling 2, trapezoidal weights");
+    fde_admm_params q3 = q;
+    q3.precond_kind = 2;
+    run(p, q3, "diagonally scaled preconditioner, Caputo order 0.7");
+    p.alpha_t = 0.0;
+    run(p, q3, "diagonally scaled preconditioner, implicit Euler");
+  }
+  {
+    fde_admm_params q3 = q;
+    q3.precond_kind = 2;
+    for (int n : sizes) run(problem(n, 6, 4), q3, "scaled preconditioner nx=" + std::to_string(n));
+    for (int n : sizes) run(problem(4, n, 6), q3, "scaled preconditioner ny=" + std::to_string(n));
+    q3.krylov_solver = 1;
+    fde_problem pk = problem(8, 8, 8);
+    fde::host::Setup sk;
+    std::string mk;
+    check(fde::host::build_setup(&pk, &q3, &sk, &mk) == FDE_EINVAL && !mk.empty(), "MINRES with kind 2 rejected");
   }
   // invalid inputs are rejected with a message, before any table is built
   std::string msg;
