@@ -1,6 +1,7 @@
 """The pure-C++ host layer (validation and table setup of the C ABI) built
-with AddressSanitizer and UndefinedBehaviorSanitizer and run over the
-supported size range, the parameter variants and invalid inputs (no GPU)."""
+with AddressSanitizer and UndefinedBehaviorSanitizer, and separately with
+ThreadSanitizer, and run over the supported size range, the parameter
+variants and invalid inputs (no GPU)."""
 import os
 import shutil
 import subprocess
@@ -23,3 +24,18 @@ def test_host_setup_under_asan_ubsan(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all checks passed" in r.stdout
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_host_setup_under_tsan(tmp_path):
+    """The same driver under ThreadSanitizer: the diagonal-scaling table of the
+    scaled preconditioner is built by several host threads."""
+    exe = str(tmp_path / "host_setup_driver_tsan")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(ROOT, "tests", "native", "host_setup_driver.cpp"), os.path.join(CSRC, "host_setup.cpp"),
+           "-o", exe, "-lpthread"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all checks passed" in r.stdout and "ThreadSanitizer" not in r.stderr
