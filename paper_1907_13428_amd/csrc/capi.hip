@@ -162,10 +162,7 @@ struct fde_ctx {
   int64_t pt_n[fde::kNumPasses] = {};
   // column-tile variants (0 widest, 1 half, 2 quarter) chosen by fde_autotune
   int tile_line_y = 0, tile_pre_y = 0, tile_pre_t = 0;
-  // PCG convergence test and step length: -1 by grid size, 0 fused into the
-  // y-forward and x-forward passes, 1 each in a one-block launch of its own
-  int conv_sep = -1;
-  int nb_xfwd = 0;  // blocks of the preconditioner's x-forward pass (set by krylov_begin)
+  int conv_sep = -1;  // PCG convergence test: -1 by grid size, 0 fused in the y-forward pass, 1 on its own
   // per-point box bounds set by fde_set_bounds (context copies; null: the scalar bound)
   double *bya = nullptr, *byb = nullptr, *bua = nullptr, *bub = nullptr;
   double *bya_mem = nullptr, *byb_mem = nullptr, *bua_mem = nullptr, *bub_mem = nullptr;
@@ -466,25 +463,15 @@ hipError_t enqueue_pcg_iteration_passes(fde_ctx* c, double* x) {
   a.rzs_partial = c->part_rz;
   a.pdir = 1;
   a.done = done;
+  a.pq_partial = c->part_pq;  // alpha computed inside the x-forward pass
+  a.pq_n = nbS;
   a.scal_w = c->scal;
   a.ints = c->ints;
-  // The step length alpha = (r, z) / (p, q) is formed inside the x-forward
-  // pass, every block summing the (p, q) partials of the y-pass of B^T; when
-  // those redundant sums would read more partials than a small launch costs
-  // (2^25, large grids), one block forms alpha on its own between the passes
-  // and the x-forward pass reads it.
-  const bool big_pq = (size_t)c->nb_xfwd * (size_t)nbS > ((size_t)1 << 25);
-  if (c->conv_sep == 1 || (c->conv_sep < 0 && big_pq)) {
-    if ((e = launch_pcg_scalar(FIN_ALPHA, c->part_pq, nbS, c->scal, c->ints, c->stream)) != hipSuccess) return e;
-  } else {
-    a.pq_partial = c->part_pq;
-    a.pq_n = nbS;
-  }
   if ((e = launch_precond_stage(a, c->fp32, 1, c->stream, &nb1, &nb5)) != hipSuccess) return e;
   // The convergence test runs inside the y-forward pass, every block summing
-  // the (r, r) partials; on large grids (x-forward blocks times H n_t above
-  // 2^25, a bound on the partial reads) one block does the test on its own
-  // between the passes.
+  // the (r, r) partials; when those redundant sums would read more than a
+  // small launch costs (about 2^21 partial reads, large grids), one block does
+  // the test on its own between the passes.
   const bool big = (size_t)nb1 * (size_t)c->H * (size_t)c->nt > ((size_t)1 << 25);
   if (c->conv_sep == 1 || (c->conv_sep < 0 && big)) {
     if ((e = launch_pcg_scalar(FIN_CONV, c->part_rr, nb1, c->scal, c->ints, c->stream)) != hipSuccess) return e;
@@ -616,7 +603,6 @@ fde_status krylov_begin(fde_ctx* c, const double* b, double* x, double tol, int 
   a.scal_w = c->scal;
   a.ints = c->ints;
   HIP_TRY(launch_precond(a, c->fp32, c->stream, &nb1, &nb5));
-  c->nb_xfwd = nb1;
   if (kr->defer) return FDE_OK;
   if (c->use_graph && !c->ptime) {
     const fde_status st = ensure_pcg_graph(c, x);

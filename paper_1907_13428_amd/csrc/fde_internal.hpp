@@ -368,10 +368,9 @@ hipError_t launch_minres_update(const MinresConsts& k, Triple z, Triple w_old, T
 
 // elementwise / reduction kernels
 // (alpha, the convergence test and beta run fused inside the passes that need them;
-// FIN_CONV and FIN_ALPHA are the stand-alone convergence test and step length
-// used when the fused forms' redundant per-block sums would cost more than one
-// small launch)
-enum PcgOp { FIN_INIT = 0, FIN_DOT, FIN_CONV, FIN_ALPHA };
+// FIN_CONV is the stand-alone convergence test used when the fused form's
+// redundant per-block sums would cost more than one small launch)
+enum PcgOp { FIN_INIT = 0, FIN_DOT, FIN_CONV };
 enum VecOp {
   VEC_RESID = 0,    // c = a - b ; partials (c,c) and (a,a)
   VEC_DOT,          // partial (a, b)

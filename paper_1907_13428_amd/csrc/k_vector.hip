@@ -59,11 +59,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_scalar(int op, const double* par
     case FIN_DOT:
       scal[kDot] = s0;
       break;
-    case FIN_ALPHA:
-      // alpha = (r, z) / (p, q) from the (p, q) partials of the y-pass of B^T
-      scal[kPQ] = s0;
-      scal[kAlpha] = scal[rz_slot(ints[kIter])] / s0;
-      break;
     case FIN_CONV: {
       scal[kRR] = s0;
       const int it = ints[kIter] + 1;
