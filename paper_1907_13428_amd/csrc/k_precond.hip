@@ -211,9 +211,14 @@ __device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int n
   __shared__ V lds[lpad_size(L) * RS];
   if (a.done && *a.done) return;
   const int H = a.H;
-  const int tiles = (H + P - 1) / P;
+  // MODE 0: the tiles of each time slice cover its H columns.  MODE 1, 2: the
+  // ny H columns (ky, kx) of a time plane are contiguous, so the tiles run
+  // over them as one list (column ky H + kx) and no tile is cut short at the
+  // end of a ky row.
+  const int ncol = MODE == 0 ? H : a.ny * H;
+  const int tiles = (ncol + P - 1) / P;
   const int tile = xcd_tile(bid, nbk);
-  const int outer = tile / tiles;  // MODE 0: time slice; MODE 1, 2: ky row
+  const int outer = MODE == 0 ? tile / tiles : 0;  // MODE 0: time slice
   const int k0 = (tile % tiles) * P;
   // element (line index i, column c) address in the spectrum
   size_t base, stride;
@@ -221,7 +226,7 @@ __device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int n
     base = (size_t)outer * a.ny * H;
     stride = H;
   } else {
-    base = (size_t)outer * H;
+    base = 0;
     stride = (size_t)a.ny * H;
   }
   V* spec = reinterpret_cast<V*>(a.spec);
@@ -240,7 +245,7 @@ __device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int n
   auto elem = [&](int k, bool& ok) -> size_t {
     const int idx = tid + k * NT;
     const int row = idx / P, c = idx % P;
-    ok = idx < NE && k0 + c < H;
+    ok = idx < NE && k0 + c < ncol;
     return base + (ok ? row * stride + c : 0) + k0;
   };
   V lv[KL];
@@ -301,9 +306,11 @@ __device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int n
     line_fft<L, E, SIGN>(v, buf, t, tw);
   } else {
     line_fft<L, E, -1>(v, buf, t, tw);
-    const int kx = k0 + g;
-    const int ky = outer;
-    const double2 lx = a.lam_x[kx < H ? kx : 0];
+    const int cf = k0 + g;  // column ky H + kx of the time plane
+    const bool in_plane = cf < ncol;
+    const int kx = in_plane ? cf % H : 0;
+    const int ky = in_plane ? cf / H : 0;
+    const double2 lx = a.lam_x[kx];
     const double2 ly = a.lam_y[ky];
     double rz = 0.0;  // this thread's share of (r, z) = sum |R|^2 / (s N)
 #pragma unroll
@@ -329,7 +336,7 @@ __device__ __forceinline__ void pre_cc_body(const PrecondArgs& a, int bid, int n
     if constexpr (MODE == 1) {
       if (a.rzs_partial) {
         // threads past the tile hold no column; columns 0 and nx/2 count once
-        const bool col = active && kx < H;
+        const bool col = active && in_plane;
         const double w = (kx == 0 || 2 * kx == a.nx) ? 1.0 : 2.0;
         const double s = block_sum<NT>(col ? w * rz : 0.0);
         if (threadIdx.x == 0) a.rzs_partial[bid] = s;
@@ -544,14 +551,14 @@ static hipError_t pre_y(const PrecondArgs& a, int sign, hipStream_t s) {
 template <int L, typename TS, int S>
 static hipError_t pre_t_S(const PrecondArgs& a, hipStream_t s) {
   using C = CCfg<L, S>;
-  const int blocks = ((a.H + C::P - 1) / C::P) * a.ny;
+  const int blocks = (a.ny * a.H + C::P - 1) / C::P;
   if (a.div_mode == 1) launch_pass(k_pre_cc<L, TS, 2, -1, S>, cc_twin<L, TS, 2, -1, S>(), blocks, C::NT, s, a);
   else launch_pass(k_pre_cc<L, TS, 1, -1, S>, cc_twin<L, TS, 1, -1, S>(), blocks, C::NT, s, a);
   return hipGetLastError();
 }
 
 template <int L, int S> static int t_blocks_S(const PrecondArgs& a) {
-  return ((a.H + CCfg<L, S>::P - 1) / CCfg<L, S>::P) * a.ny;
+  return (a.ny * a.H + CCfg<L, S>::P - 1) / CCfg<L, S>::P;
 }
 
 template <int L> static int t_blocks(const PrecondArgs& a) {
