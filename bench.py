@@ -14,10 +14,12 @@ iteration cap --full-cap) is timed as well, FP64 and with the FP32
 preconditioner; at this grid and delta = rho = 1 the ADMM residual on the
 control copy falls slowly, so the cap is normally reached and the record says
 so ("converged": false, residuals).  Each PCG pass is timed with HIP events
-for the roofline figure of the dominant kernel.  The batched leg runs 64
-uneven instances for a fixed ADMM budget each, concurrently with the FP32
-preconditioner and sequentially in FP64 ("solves" = budgeted runs).  The
-CPU oracle's PCG iteration on the same grid is timed on a bounded sample.
+for the roofline figure of the dominant kernel.  The batched legs run many
+uneven instances for a fixed ADMM budget each (instances_per_s counts these
+budgeted runs, not converged solves): in lockstep, stream-per-instance
+concurrently, each in FP64 and with the FP32 preconditioner, and sequentially
+in FP64.  The CPU oracle's PCG iteration on the same grid is timed on a
+bounded sample.
 Prints one JSON line.
 """
 import argparse
@@ -393,7 +395,7 @@ def batch_modes(fde, torch, ws, cap, modes):
             _, stats, _ = b.solve(yh, concurrent=(mode != "sequential"), lockstep=(mode == "lockstep"))
             dt = time.perf_counter() - t0
         pcg = sum(s["pcg_total"] for s in stats)
-        rec[tag] = {"s": round(dt, 3), "solves_per_s": round(len(ws) / dt, 2), "pcg_iters_per_s": round(pcg / dt, 1),
+        rec[tag] = {"s": round(dt, 3), "instances_per_s": round(len(ws) / dt, 2), "pcg_iters_per_s": round(pcg / dt, 1),
                     "pcg_total": pcg}
     return rec
 
