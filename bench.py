@@ -60,6 +60,9 @@ def parse():
                     help="only sweep the ADMM settings (psi scaling of the u copies, delta, rho) on the headline "
                          "grid: iterations and time to the 1e-4 and 1e-6 stopping tests; prints one JSON line")
     ap.add_argument("--sweep-cap", type=int, default=3000, help="ADMM iteration cap per setting of --admm-sweep")
+    ap.add_argument("--lockstep-only", choices=["small", "mid"],
+                    help="only the lockstep batch, FP64: the 256 small instances or the 64 mid-size ones, "
+                         "--batch-cap ADMM iterations each; prints one JSON line (for kernel traces)")
     ap.add_argument("--passes-only", choices=["headline", "headline_fp32", "precision", "precision_fp32"],
                     help="only the in-solve per-pass timing on that grid (warmup W, then K timed ADMM "
                          "iterations); prints one JSON line (for kernel traces and counters)")
@@ -455,6 +458,13 @@ def main():
         return
     if a.passes_only:
         print(json.dumps(passes_only_leg(fde, torch, a.passes_only, a.warmup, a.steps)), flush=True)
+        return
+    if a.lockstep_only:
+        import workloads as W
+
+        ws = W.batched_small() if a.lockstep_only == "small" else W.batched()
+        rec = batch_modes(fde, torch, ws, a.batch_cap, (("lockstep_fp64", 0, "lockstep"),))
+        print(json.dumps({"lockstep": a.lockstep_only, **rec}), flush=True)
         return
     out = {"metric": "PCG iters/s + ADMM solve time, 256^2x64 grid; HBM GB/s; FP32-precond vs FP64",
            "unit": "PCG iters/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
