@@ -199,10 +199,13 @@ constexpr int pick_radix(int rem, int E) {
 // 256 points; 8 elements elsewhere, so that long lines keep their register
 // footprint low and use 2 or 4 wavefronts with block barriers; lengths with
 // a factor 5 take 20 or 10, which hold the radices 4, 5 and 2 of 50, 80,
-// 100 and 160)
+// 100 and 160; 16 and 48 points take 4 threads per line and 24 points 2, so
+// that the passes over small grids spread over more blocks)
 constexpr int default_E(int L) {
   return (L % 5 == 0) ? ((L % 20 == 0) ? 20 : 10)
+         : (L == 24 || L == 48) ? 12
          : (L % 3 == 0) ? (L >= 24 ? 24 : L)
+         : (L == 16) ? 4
          : (L <= 16)  ? L
          : (L == 128) ? 16
                                   : 8;

@@ -108,6 +108,7 @@ __device__ __forceinline__ void xpass_body(const LinePassArgs& a, int bid) {
   }
   line_sync<WAVE>();
 
+  static_assert(E % 4 == 0, "the epilogue moves pairs of elements of both halves");
   constexpr int KE = E / 4;                    // element pairs per thread (L / 4 = T E / 4)
   constexpr int KG = (KE % 2 == 0) ? 2 : KE;   // element pairs per load group
   const size_t plane = (size_t)a.ny * n;
