@@ -496,14 +496,23 @@ def main():
     # plain launches with HIP events bound to each pass's own dispatch.
     progress(f"pass timing over {a.steps} ADMM iterations")
     passes = in_solve_passes(ctx, yhat, state, torch)
-    dom = max(passes, key=lambda k: passes[k]["share"])
+    # The dominant pass has the largest share of the passes' GPU time.  Passes
+    # within 2% of that share are a tie (at the headline the y-pass of B^T and
+    # the preconditioner's x-forward pass): the roofline then names the one
+    # furthest from its peak and lists the others beside it.
+    top = max(p["share"] for p in passes.values())
+    tied = [k for k in passes if passes[k]["share"] >= 0.98 * top]
+    dom = min(tied, key=lambda k: passes[k]["GB/s"])
     copy = copy_calibration(torch)
     achieved = passes[dom]["GB/s"]
     out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": measured_traffic(dom, out["autotune"][0]),
                        "bytes_per_launch": passes[dom]["bytes"], "us_per_launch": passes[dom]["us"],
-                       "launches": passes[dom]["launches"], "copy_kernel": copy}
+                       "launches": passes[dom]["launches"], "copy_kernel": copy,
+                       "tied_with": {k: {"share": passes[k]["share"], "GB/s": passes[k]["GB/s"],
+                                         "frac": round(passes[k]["GB/s"] / HBM_PEAK_GBS, 4)}
+                                     for k in tied if k != dom}}
     out["pcg_iteration_passes"] = passes
     # The line passes are FP64-VALU-heavy FFTs: nominal FFT flops (5 L log2 L
     # per complex transform of length L = 2n) per launch against the FP64
